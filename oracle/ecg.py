@@ -1,0 +1,352 @@
+"""FP64 oracle of flexibly enlarged CG (TEST INFRASTRUCTURE ONLY).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this module.  It is deliberately plain: NumPy/SciPy
+products, LAPACK QR and Cholesky, no blocking or fusion.
+
+What it follows
+---------------
+* The enlarged Krylov subspace and the split operator T^t (Section 1 and
+  Section 2; the matrix [T^t(v)] of eq. (Tt) in Section 4): column j of
+  [T^t(v)] holds the entries of v on subdomain delta_j and zeros elsewhere.
+* SRE-CG2 (Section 2.1, Algorithm 1) and its flexible form (Section 4.3,
+  Algorithm 3): W_1 = [T^t(r_0)]; W_k = A W_{k-1}, or [T^{t/2}(r_{k-1})] at a
+  switch; W_k is A-orthonormalised against all stored blocks Q (or the last
+  ``trunc`` blocks, Section 3) and then against itself; alpha_k = W_k^T r_{k-1},
+  x_k = x_{k-1} + W_k alpha_k, r_k = r_{k-1} - A W_k alpha_k.
+* The switch test (Section 4.2): tol1 = |rho_k - rho_{k-1}| / rho_0, tested at
+  the start of the next iteration; the halved partition merges subdomains 2i
+  and 2i+1 (Section 4, definition of delta-tilde), i.e. ``part >> level``.
+* Split preconditioning, option 2 (Section 4.5, eq. (zsre2)): the recurrences
+  are unchanged and only the candidate block changes:
+  L^{-T}[T(L^{-1} r)] at k = 1 and at a switch, M^{-1} A W_{k-1} otherwise.
+* A-orthonormalisation (Section 5 names CGS2 and Pre-CholQR): against Q,
+  two classical Gram-Schmidt passes in the A inner product,
+  W <- W - Q (Q^T A W); then Pre-CholQR: a Euclidean thin QR W = W_hat R with
+  positive diagonal, followed by S = W_hat^T A W_hat = C^T C (Cholesky) and
+  W <- W_hat C^{-1}.
+
+Readings where the paper is silent (stated again in the design notes):
+* the absolute value in tol1 (the algorithms omit it, the text has it);
+* rank deficiency: a column is dropped (deflated) when, in either QR step,
+  its Schur-complement pivot is <= deflate_tol times its own diagonal entry;
+  a block whose columns are all dropped ends the solve (status "breakdown");
+* repeated halving (rule REPEAT) and forced switch iterations (SCHEDULE)
+  generalise the paper's single switch.
+
+Bookkeeping: ``it`` = completed iterations, ``switch_iters`` = iterations at
+which a halved block was formed, ``mem`` = total stored columns (for one
+switch this equals t*sIt + (t/2)*(It - sIt) with sIt = switch_iter - 1).
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.linalg as sla
+
+REDUCE_NONE = 0
+REDUCE_ONCE = 1
+REDUCE_REPEAT = 2
+REDUCE_SCHEDULE = 3
+
+
+def split(v: np.ndarray, part: np.ndarray, t: int) -> np.ndarray:
+    """[T^t(v)]: n x t matrix, column j = v restricted to subdomain j (eq. (Tt))."""
+    n = v.shape[0]
+    out = np.zeros((n, t))
+    out[np.arange(n), part] = v
+    return out
+
+
+def merged_partition(part: np.ndarray, level: int) -> np.ndarray:
+    """Subdomain map after ``level`` halvings: delta-tilde_i = delta_{2i} U delta_{2i+1}."""
+    return np.asarray(part) >> level
+
+
+def _cholesky_pivot(S: np.ndarray) -> float:
+    """Last pivot of the Cholesky factorisation of S (the Schur complement of the
+    last diagonal entry), or -inf when the leading block is not positive definite."""
+    try:
+        c = np.linalg.cholesky(S)
+    except np.linalg.LinAlgError:
+        return -np.inf
+    return float(c[-1, -1] ** 2)
+
+
+def _select_columns(gram: np.ndarray, tau: float):
+    """Greedy left-to-right column selection on a Gram matrix.
+
+    Column j is kept when the Cholesky pivot of gram restricted to the kept
+    columns plus j exceeds tau * gram[j, j].  tau < 0 keeps every column and
+    reports failure instead (returns None) when a pivot is not positive.
+    """
+    m = gram.shape[0]
+    d = np.diag(gram)
+    try:  # common case: every column passes, one factorisation gives all pivots
+        piv = np.diag(np.linalg.cholesky(gram)) ** 2
+        if np.all(d > 0) and np.all(piv > (tau if tau > 0 else 0.0) * d):
+            return list(range(m))
+    except np.linalg.LinAlgError:
+        pass
+    keep = []
+    for j in range(m):
+        idx = keep + [j]
+        p = _cholesky_pivot(gram[np.ix_(idx, idx)]) if d[j] > 0 else -np.inf
+        if tau < 0:
+            if not p > 0:
+                return None
+            keep.append(j)
+        elif p > tau * d[j] and d[j] > 0:
+            keep.append(j)
+    return keep
+
+
+def euclidean_qr(W: np.ndarray, tau: float):
+    """Thin Householder QR with positive diagonal, dropping dependent columns.
+
+    Column j is dropped when its distance to the span of the previously kept
+    columns, squared, is <= tau * ||w_j||^2.  Returns (W_hat, kept indices), or
+    (None, None) when tau < 0 and W is numerically rank deficient.
+    """
+    nrm2 = np.einsum("ij,ij->j", W, W)
+    m = W.shape[1]
+    Qh, R = np.linalg.qr(W)
+    d2 = np.diag(R) ** 2
+    if np.all(nrm2 > 0) and np.all(d2 > (tau if tau > 0 else 0.0) * nrm2):
+        keep = list(range(m))  # every prefix pivot passes: nothing to drop
+    else:
+        keep = []
+        for j in range(m):
+            if not nrm2[j] > 0:
+                if tau < 0:
+                    return None, None
+                continue
+            _, Rj = np.linalg.qr(W[:, keep + [j]])
+            dj = Rj[-1, -1] ** 2
+            if tau < 0:
+                if not dj > 0:
+                    return None, None
+                keep.append(j)
+            elif dj > tau * nrm2[j]:
+                keep.append(j)
+        if not keep:
+            return np.zeros((W.shape[0], 0)), keep
+        Qh, R = np.linalg.qr(W[:, keep])
+    s = np.sign(np.diag(R))
+    s[s == 0] = 1.0
+    return Qh * s[None, :], keep
+
+
+def a_orthonormalize_self(W: np.ndarray, A, tau: float):
+    """Pre-CholQR in the A inner product with deflation.
+
+    Returns the A-orthonormal block (n x t_eff) or None on breakdown (tau < 0).
+    """
+    What, keep = euclidean_qr(W, tau)
+    if What is None:
+        return None
+    if What.shape[1] == 0:
+        return What
+    S = What.T @ (A @ What)
+    S = 0.5 * (S + S.T)
+    keep2 = _select_columns(S, tau)
+    if keep2 is None:
+        return None
+    if not keep2:
+        return np.zeros((W.shape[0], 0))
+    S2 = S[np.ix_(keep2, keep2)]
+    C = np.linalg.cholesky(S2).T  # upper, S2 = C^T C
+    # W = W_hat C^{-1}  <=>  C^T W^T = W_hat^T
+    return sla.solve_triangular(C, What[:, keep2].T, trans="T", lower=False).T
+
+
+def a_orthonormalize_against(W: np.ndarray, Qm: np.ndarray, A) -> np.ndarray:
+    """CGS2 in the A inner product: two passes of W <- W - Q (Q^T A W)."""
+    for _ in range(2):
+        W = W - Qm @ (Qm.T @ (A @ W))
+    return W
+
+
+class SplitPreconditioner:
+    """M = L L^T given by two block operators: linv(X) = L^{-1} X, linvT(X) = L^{-T} X."""
+
+    def __init__(self, linv, linvT):
+        self.linv = linv
+        self.linvT = linvT
+
+    def minv(self, X):
+        return self.linvT(self.linv(X))
+
+
+@dataclass
+class EcgResult:
+    x: np.ndarray
+    it: int
+    switch_iters: list
+    widths: list
+    rho: list
+    status: str
+    t_final: int
+    deflated: int
+    iterates: list = field(default_factory=list)
+    blocks: list = field(default_factory=list)
+    residuals: list = field(default_factory=list)
+
+    @property
+    def mem(self) -> int:
+        return int(sum(self.widths))
+
+    @property
+    def sit(self) -> int:
+        """Iterations run at the initial width (the paper's sIt)."""
+        return (self.switch_iters[0] - 1) if self.switch_iters else self.it
+
+    @property
+    def relres(self) -> float:
+        return self.rho[-1] / self.rho[0] if self.rho[0] > 0 else 0.0
+
+
+def _switch_now(rule, k, tol1, switch_tol, t_cur, t_min, switches, min_gap, schedule):
+    if t_cur % 2 or t_cur // 2 < max(t_min, 1):
+        return False
+    if rule == REDUCE_NONE:
+        return False
+    if rule == REDUCE_SCHEDULE:
+        return k in schedule
+    if not tol1 < switch_tol:
+        return False
+    if rule == REDUCE_ONCE:
+        return not switches
+    if rule == REDUCE_REPEAT:
+        return (not switches) or (k - switches[-1] >= min_gap)
+    raise ValueError(rule)
+
+
+def flexible_sre_cg2(A, b, part, t, *, x0=None, tol=1e-8, kmax=20000, reduce=REDUCE_NONE,
+                     switch_tol=1e-5, t_min=1, min_gap=1, schedule=(), trunc=0,
+                     deflate_tol=1e-14, precond: SplitPreconditioner | None = None,
+                     record=False, candidate="sre") -> EcgResult:
+    """Flexibly SRE-CG2 (Algorithm 3); with reduce=REDUCE_NONE it is SRE-CG2
+    (Algorithm 1), with trunc>0 the truncated SRE-CG2 of Section 3.
+
+    A: anything with ``A @ X`` (dense array or scipy sparse), SPD, n x n.
+    part: int array, subdomain of each unknown, values in [0, t).
+    candidate: "sre" (W_k = A W_{k-1}) or "modified-msdo" (W_k = [T^t(r_{k-1})],
+      the modified MSDO-CG of Section 2.2).
+    """
+    b = np.asarray(b, dtype=np.float64)
+    part = np.asarray(part)
+    n = b.shape[0]
+    x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
+    r = b - A @ x
+    rho0 = float(np.linalg.norm(r))
+    res = EcgResult(x=x, it=0, switch_iters=[], widths=[], rho=[rho0], status="converged",
+                    t_final=t, deflated=0)
+    if rho0 == 0.0:
+        return res
+    schedule = set(int(s) for s in schedule)
+    rho_prev = rho0
+    tol1 = 1.0
+    k = 1
+    level = 0
+    t_cur = t
+    blocks = []
+    colstart = []  # first column of each stored block inside Qbuf
+    Qbuf = np.zeros((n, 4 * t), order="F")  # all stored blocks, column-major
+    ncols = 0
+    Z_prev = None
+    pre = precond
+
+    def from_residual(rv, lvl, width):
+        if pre is None:
+            return split(rv, merged_partition(part, lvl), width)
+        return pre.linvT(split(pre.linv(rv), merged_partition(part, lvl), width))
+
+    while rho_prev > tol * rho0 and k < kmax:
+        if k == 1:
+            cand = from_residual(r, 0, t_cur)
+        elif _switch_now(reduce, k, tol1, switch_tol, t_cur, t_min, res.switch_iters, min_gap,
+                         schedule):
+            level += 1
+            t_cur //= 2
+            res.switch_iters.append(k)
+            cand = from_residual(r, level, t_cur)
+        elif candidate == "modified-msdo":
+            cand = from_residual(r, level, t_cur)
+        else:
+            cand = Z_prev if pre is None else pre.minv(Z_prev)
+        if blocks:
+            # Q = all stored blocks, or the last `trunc` of them (Section 3)
+            first = 0 if trunc <= 0 else colstart[max(len(blocks) - trunc, 0)]
+            cand = a_orthonormalize_against(cand, Qbuf[:, first:ncols], A)
+        W = a_orthonormalize_self(cand, A, deflate_tol)
+        if W is None or W.shape[1] == 0:
+            res.status = "breakdown"
+            break
+        alpha = W.T @ r
+        x = x + W @ alpha
+        Z = A @ W
+        r = r - Z @ alpha
+        rho = float(np.linalg.norm(r))
+        tol1 = abs(rho - rho_prev) / rho0
+        rho_prev = rho
+        res.rho.append(rho)
+        res.widths.append(W.shape[1])
+        res.deflated += cand.shape[1] - W.shape[1]
+        blocks.append(W)
+        colstart.append(ncols)
+        if ncols + W.shape[1] > Qbuf.shape[1]:
+            grown = np.zeros((n, max(2 * Qbuf.shape[1], ncols + W.shape[1])), order="F")
+            grown[:, :ncols] = Qbuf[:, :ncols]
+            Qbuf = grown
+        Qbuf[:, ncols:ncols + W.shape[1]] = W
+        ncols += W.shape[1]
+        Z_prev = Z
+        if record:
+            res.iterates.append(x.copy())
+            res.residuals.append(r.copy())
+        k += 1
+    res.x = x
+    res.it = k - 1
+    res.t_final = t_cur
+    if res.status != "breakdown" and rho_prev > tol * rho0:
+        res.status = "not_converged"
+    if record:
+        res.blocks = blocks
+    return res
+
+
+def cg(A, b, x0=None, tol=1e-8, kmax=100000, record=False):
+    """Classical CG (Hestenes-Stiefel), the t = 1 special case (Section 1)."""
+    b = np.asarray(b, dtype=np.float64)
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
+    r = b - A @ x
+    p = r.copy()
+    rr = float(r @ r)
+    rho0 = np.sqrt(rr)
+    its = []
+    k = 0
+    while np.sqrt(rr) > tol * rho0 and k < kmax:
+        Ap = A @ p
+        a = rr / float(p @ Ap)
+        x = x + a * p
+        r = r - a * Ap
+        rr_new = float(r @ r)
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+        k += 1
+        if record:
+            its.append(x.copy())
+    return x, k, its
+
+
+def true_relres(A, b, x) -> float:
+    """||b - A x|| / ||b|| in FP64."""
+    return float(np.linalg.norm(b - A @ x) / np.linalg.norm(b))
+
+
+def memory_formula(t: int, it: int, sit: int) -> int:
+    """Stored vectors with one halving at iteration sit+1 (Section 5.2 tables)."""
+    return t * sit + (t // 2) * (it - sit)

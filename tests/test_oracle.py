@@ -1,0 +1,241 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Nothing here re-types the oracle's own formulas: each check uses an
+independent definition (50-digit subspace projections, dense direct solves,
+LAPACK/CG references) or a property the paper states.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import brute, ecg
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def tiny(n=40, t=4, kappa=50.0, seed=1):
+    A = W.random_spd(n, kappa, seed)
+    b = W.rhs_uniform(n, seed + 1)
+    part = W.random_partition(n, t, seed + 2)
+    return A, b, part
+
+
+# ---------------------------------------------------------------- split operator
+def test_split_sums_back_and_is_disjoint():
+    # T^t(v) 1_t = v (proof of Theorem 2) and one nonzero per row (eq. (Tt))
+    rng = np.random.default_rng(0)
+    v = rng.standard_normal(50)
+    part = W.random_partition(50, 8, 1)
+    T = ecg.split(v, part, 8)
+    assert np.array_equal(T.sum(axis=1), v)
+    assert np.all((T != 0).sum(axis=1) <= 1)
+    for j in range(8):
+        assert np.array_equal(T[part == j, j], v[part == j])
+
+
+def test_halving_merges_consecutive_pairs():
+    # delta-tilde_i = delta_{2i-1} U delta_{2i} (1-based) -> id >> 1 (0-based)
+    part = np.arange(16, dtype=np.int32)
+    merged = ecg.merged_partition(part, 1)
+    assert list(merged) == [i // 2 for i in range(16)]
+    rng = np.random.default_rng(3)
+    v = rng.standard_normal(16)
+    assert np.array_equal(ecg.split(v, merged, 8), ecg.split(v, part, 16).reshape(16, 8, 2).sum(axis=2))
+
+
+def test_box_partition_halving_keeps_boxes():
+    # Morton numbering: part >> 1 of a 4x8 box layout is the 4x4 box layout
+    p8 = W.box_partition((64, 64), (4, 8))
+    p4 = W.box_partition((64, 64), (4, 4))
+    # same sets up to relabelling
+    pairs = set(zip((p8 >> 1).tolist(), p4.tolist()))
+    assert len(pairs) == 16
+    assert len({a for a, _ in pairs}) == 16
+
+
+# ---------------------------------------------------------------- iterates vs definitions
+def test_iterates_equal_krylov_galerkin_projection():
+    # x_k is the Galerkin iterate on x0 + K_{k,t}(A, r0) (Section 2), 50 digits
+    A, b, part = tiny()
+    res = ecg.flexible_sre_cg2(A, b, part, 4, tol=1e-14, record=True)
+    for k in (1, 2, 4, 7):
+        xk = brute.krylov_projection(A, b, part, 4, k)
+        assert np.linalg.norm(res.iterates[k - 1] - xk) <= 1e-12 * np.linalg.norm(xk)
+
+
+def test_flexible_iterates_equal_subspace_recursion():
+    # with a switch at k=4: the subspaces Algorithm 3 builds, defined basis-free
+    A, b, part = tiny(n=40, t=8, seed=5)
+    res = ecg.flexible_sre_cg2(A, b, part, 8, tol=1e-14, reduce=ecg.REDUCE_SCHEDULE,
+                               schedule=[4], t_min=1, record=True)
+    assert res.switch_iters == [4]
+    xs = brute.recursion_projection(A, b, part, 8, 6, [4])
+    for k in range(6):
+        assert np.linalg.norm(res.iterates[k] - xs[k]) <= 1e-12 * np.linalg.norm(xs[k])
+    assert res.widths[:6] == [8, 8, 8, 4, 4, 4]
+
+
+def test_t1_is_cg():
+    # Theorem 2 with t = 1: the enlarged subspace is the Krylov subspace
+    A, b, _ = tiny(n=30, t=1)
+    part = np.zeros(30, dtype=np.int32)
+    res = ecg.flexible_sre_cg2(A, b, part, 1, tol=1e-14, record=True)
+    xs = brute.cg_iterates(A, b, 12)
+    for k in range(12):
+        assert np.linalg.norm(res.iterates[k] - xs[k]) <= 1e-11 * np.linalg.norm(xs[k])
+
+
+def test_dense_direct_solve():
+    A, b, part = tiny(n=48, t=6, kappa=1e3, seed=7)
+    res = ecg.flexible_sre_cg2(A, b, part, 6, tol=1e-12)
+    x = np.linalg.solve(A, b)
+    assert res.status == "converged"
+    assert np.linalg.norm(res.x - x) <= 1e-9 * np.linalg.norm(x)
+
+
+# ---------------------------------------------------------------- Petrov-Galerkin invariants
+def test_a_orthonormal_basis_and_galerkin_condition():
+    A, b, part = tiny(n=64, t=4, kappa=1e3, seed=11)
+    res = ecg.flexible_sre_cg2(A, b, part, 4, tol=1e-10, record=True)
+    Q = np.hstack(res.blocks)
+    assert np.abs(Q.T @ A @ Q - np.eye(Q.shape[1])).max() <= 1e-12
+    for k in range(1, len(res.blocks) + 1):
+        Qk = np.hstack(res.blocks[:k])
+        rk = b - A @ res.iterates[k - 1]
+        assert np.linalg.norm(Qk.T @ rk) <= 1e-12 * np.linalg.norm(b)
+        # x_k - x_0 = Q_k Q_k^T r_0 (A-orthonormal basis of the search space)
+        assert np.linalg.norm(res.iterates[k - 1] - Qk @ (Qk.T @ b)) <= 1e-11 * np.linalg.norm(res.iterates[k - 1])
+
+
+def test_monotone_a_norm_error_and_not_worse_than_cg():
+    # nested subspaces (Section 2) and K_k subset of K_{k,t} (Theorem 2)
+    A, b, part = tiny(n=48, t=4, kappa=1e3, seed=13)
+    xs = np.linalg.solve(A, b)
+    res = ecg.flexible_sre_cg2(A, b, part, 4, tol=1e-12, record=True)
+    _, _, cgit = ecg.cg(A, b, tol=1e-30, kmax=len(res.iterates), record=True)
+    errs = [brute.a_norm_error(A, xs, x) for x in res.iterates]
+    assert all(e2 <= e1 * (1 + 1e-10) for e1, e2 in zip(errs, errs[1:]))
+    for k in range(len(res.iterates)):
+        assert errs[k] <= brute.a_norm_error(A, xs, cgit[k]) * (1 + 1e-8) + 1e-12
+
+
+@pytest.mark.parametrize("n,t", [(48, 4), (45, 5), (50, 4)])
+def test_termination_in_ceil_n_over_t(n, t):
+    # exact arithmetic + full rank: the subspace is all of R^n after ceil(n/t) blocks;
+    # when t does not divide n the last block has dependent columns and is deflated
+    A, b, part = tiny(n=n, t=t, kappa=30.0, seed=17)
+    res = ecg.flexible_sre_cg2(A, b, part, t, tol=1e-11)
+    assert res.status == "converged"
+    assert res.it == -(-n // t)
+    assert res.mem == n
+    assert res.deflated == (t * res.it - n)
+
+
+# ---------------------------------------------------------------- truncation (Section 3)
+def test_truncation_two_blocks_matches_full_early():
+    # Section 2.1: W_k = A W_{k-1} need only be A-orthonormalised against the two
+    # previous blocks in exact arithmetic (SRE-CG = truncated SRE-CG2 with trunc = 2)
+    A, b, part = tiny(n=60, t=4, kappa=20.0, seed=19)
+    full = ecg.flexible_sre_cg2(A, b, part, 4, tol=1e-12, record=True)
+    tr = ecg.flexible_sre_cg2(A, b, part, 4, tol=1e-12, trunc=2, record=True)
+    for k in range(6):
+        assert np.linalg.norm(full.iterates[k] - tr.iterates[k]) <= 1e-9 * np.linalg.norm(full.iterates[k])
+
+
+# ---------------------------------------------------------------- memory bookkeeping
+def _golden_rows():
+    rows = []
+    with open(os.path.join(GOLDEN, "paper_flex_sre_cg2.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            m, t, tol, it, sit, mem = line.split()
+            rows.append((m, int(t), tol, int(it), int(sit), int(mem)))
+    return rows
+
+
+def test_memory_formula_reproduces_paper_tables():
+    rows = _golden_rows()
+    assert len(rows) == 96
+    for m, t, tol, it, sit, mem in rows:
+        assert ecg.memory_formula(t, it, sit) == mem, (m, t, tol)
+
+
+def test_oracle_memory_matches_its_switch_bookkeeping():
+    p = W.config("poisson64")
+    A = p.A.to_scipy()
+    res = ecg.flexible_sre_cg2(A, p.b, p.part, p.t, reduce=ecg.REDUCE_ONCE, switch_tol=1e-4, t_min=2)
+    assert len(res.switch_iters) == 1 and res.deflated == 0
+    assert res.mem == ecg.memory_formula(p.t, res.it, res.sit)
+
+
+def test_switch_rule_uses_absolute_change():
+    # tol1 = |rho_k - rho_{k-1}| / rho_0: the residual norm may rise, which must
+    # not trigger a switch (without the absolute value every run would switch at k=2)
+    A, b, part = tiny(n=48, t=8, kappa=1e3, seed=23)
+    res = ecg.flexible_sre_cg2(A, b, part, 8, tol=1e-10, reduce=ecg.REDUCE_ONCE, switch_tol=1e-6, t_min=1)
+    rho = np.array(res.rho)
+    d = np.abs(np.diff(rho)) / rho[0]
+    if res.switch_iters:
+        k = res.switch_iters[0]
+        assert d[k - 2] < 1e-6 and np.all(d[: k - 2] >= 1e-6)
+    else:
+        assert np.all(d[:-1] >= 1e-6)
+
+
+def test_repeated_halving_reaches_t_min():
+    p = W.config("jump3d160", scale=8)
+    A = p.A.to_scipy()
+    res = ecg.flexible_sre_cg2(A, p.b, p.part, p.t, reduce=ecg.REDUCE_REPEAT, switch_tol=1e-2, t_min=8,
+                               kmax=400)
+    widths = sorted(set(res.widths), reverse=True)
+    assert widths[0] == 64 and widths[-1] >= 8
+    assert all(w in (64, 32, 16, 8) for w in widths)
+    assert res.t_final == widths[-1]
+
+
+# ---------------------------------------------------------------- deflation and failures
+def test_zero_subdomain_residual_is_deflated():
+    A, b, part = tiny(n=40, t=4, seed=29)
+    b = b.copy()
+    b[part == 2] = 0.0
+    res = ecg.flexible_sre_cg2(A, b, part, 4, tol=1e-10)
+    assert res.widths[0] == 3 and res.status == "converged"
+    x = np.linalg.solve(A, b)
+    assert np.linalg.norm(res.x - x) <= 1e-8 * np.linalg.norm(x)
+
+
+def test_breakdown_without_deflation():
+    A, b, part = tiny(n=40, t=4, seed=29)
+    b = b.copy()
+    b[part == 2] = 0.0
+    res = ecg.flexible_sre_cg2(A, b, part, 4, tol=1e-10, deflate_tol=-1.0)
+    assert res.status == "breakdown"
+
+
+def test_kmax_gives_not_converged():
+    # the loop guard is k < k_max (Algorithm 3), so at most k_max - 1 iterations
+    A, b, part = tiny(n=48, t=4, kappa=1e3, seed=31)
+    res = ecg.flexible_sre_cg2(A, b, part, 4, tol=1e-12, kmax=3)
+    assert res.it == 2 and res.status == "not_converged"
+
+
+# ---------------------------------------------------------------- preconditioning (Section 4.5)
+def test_split_preconditioned_equals_run_on_transformed_system():
+    # option 2 (modified recurrences on Z_k = L^{-T} Z-hat_k) reproduces option 1
+    # (the method on A-hat = L^{-1} A L^{-T}, b-hat = L^{-1} b, x = L^{-T} x-hat)
+    A, b, part = tiny(n=40, t=4, kappa=1e3, seed=37)
+    rng = np.random.default_rng(5)
+    L = np.tril(rng.uniform(-0.3, 0.3, (40, 40)), -1) + np.diag(rng.uniform(1.0, 2.0, 40))
+    Linv = np.linalg.inv(L)
+    Ah = Linv @ A @ Linv.T
+    bh = Linv @ b
+    hat = ecg.flexible_sre_cg2(Ah, bh, part, 4, tol=1e-30, kmax=6, record=True)
+    pre = ecg.SplitPreconditioner(lambda X: Linv @ X, lambda X: Linv.T @ X)
+    res = ecg.flexible_sre_cg2(A, b, part, 4, tol=1e-30, kmax=6, record=True, precond=pre)
+    for k in range(5):
+        xk = Linv.T @ hat.iterates[k]
+        assert np.linalg.norm(res.iterates[k] - xk) <= 1e-10 * np.linalg.norm(xk)
