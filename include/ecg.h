@@ -1,0 +1,230 @@
+/*
+ * ecg.h - C ABI of the MI355X (gfx950) flexibly enlarged Conjugate Gradient solver.
+ *
+ * The method is flexibly SRE-CG2 (Section 4.3, Algorithm 3 of "Flexibly Enlarged
+ * Conjugate Gradient methods"): the residual is split over t subdomains
+ * (operator T^t, eq. (Tt)); every iteration adds a block of t search vectors that is
+ * A-orthonormalised against the stored blocks (CGS2) and against itself (Pre-CholQR,
+ * Section 5); x and r follow the short recurrences of Algorithm 1; once the relative
+ * change of the residual norm falls below switchTol the block width is halved and the
+ * next block is T^{t/2}(r) on merged subdomains (Section 4.2).
+ *
+ * Conventions for every entry point:
+ *  - Every function returns ecg_status.  Nothing throws across the ABI.  On a status
+ *    other than ECG_OK / ECG_ENOTCONV, ecg_last_error() returns a message describing
+ *    the failure (thread-local, valid until the next call on the same thread).
+ *  - Pointers documented as "device" must point to device memory of the current HIP
+ *    device (e.g. from hipMalloc or a torch tensor on cuda:0); "host" pointers to host
+ *    memory.  Arrays are dense, contiguous, in the stated element type.
+ *  - hip_stream is a hipStream_t (NULL = the default stream).  All device work is
+ *    enqueued on it.  Functions return after the work they describe has completed
+ *    unless stated otherwise.
+ *  - Invalid arguments are rejected with ECG_EINVAL before any device work.
+ *    A HIP runtime error gives ECG_EHIP with the HIP error string in ecg_last_error().
+ *  - Opaque objects are owned by the library and freed by their *_destroy function.
+ *
+ * Block layout: an n x t block of vectors is stored row-major ("[n][t]": the t values
+ * of one unknown are contiguous).  The solver uses this layout internally; it is
+ * visible to callers only through ecg_debug_* entry points.
+ */
+#ifndef ECG_H
+#define ECG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ECG_OK = 0,
+  ECG_ENOTCONV = 1,      /* k_max reached before the tolerance; x and report are valid */
+  ECG_EINVAL = -1,       /* invalid argument (nothing was enqueued) */
+  ECG_ENOMEM = -2,       /* workspace too small or library allocation failed */
+  ECG_EHIP = -3,         /* HIP runtime error */
+  ECG_EBREAKDOWN = -4    /* a block lost every column (all deflated), or a t x t Cholesky
+                            pivot was not positive with deflation disabled; x and report
+                            hold the last completed iterate */
+} ecg_status;
+
+typedef enum {
+  ECG_REDUCE_NONE = 0,            /* SRE-CG2, Algorithm 1: t never changes */
+  ECG_REDUCE_SWITCHTOL_ONCE = 1,  /* Algorithm 3: halve t once, when tol1 < switch_tol */
+  ECG_REDUCE_SWITCHTOL_REPEAT = 2,/* halve again at each later tol1 < switch_tol, at least
+                                     min_gap iterations apart, down to t_min */
+  ECG_REDUCE_SCHEDULE = 3         /* halve exactly at the iterations listed in schedule */
+} ecg_reduce;
+
+typedef enum {
+  ECG_FP64 = 0,          /* every step in FP64 */
+  ECG_FP32_REFINED = 1   /* SpMM, Gram products and block updates in FP32 (FP32
+                            accumulation); t x t Grams, Cholesky factors, x, the true
+                            residual and the outer refinement in FP64 */
+} ecg_precision;
+
+typedef enum {
+  ECG_PRECOND_NONE = 0,
+  ECG_PRECOND_SPLIT = 1  /* split preconditioner M = L L^T given as an ecg_precond
+                            (Section 4.5, option 2, eq. (zsre2)) */
+} ecg_precond_kind;
+
+typedef struct ecg_operator ecg_operator;    /* device copy of a sparse matrix (CSR) */
+typedef struct ecg_partition ecg_partition;  /* device copy of the subdomain map */
+typedef struct ecg_precond ecg_precond;      /* split preconditioner M = L L^T */
+
+typedef struct {
+  double tol;              /* stop when ||r_k|| <= tol * ||r_0|| (recursive residual) */
+  int32_t kmax;            /* loop runs while k < kmax (at most kmax-1 iterations) */
+  int32_t reduce;          /* ecg_reduce */
+  double switch_tol;       /* switchTol of Section 4.2 */
+  int32_t t_min;           /* never halve below this width (>= 1) */
+  int32_t min_gap;         /* REPEAT: iterations between two halvings (>= 1) */
+  const int32_t* schedule; /* host; SCHEDULE: iterations k at which to halve */
+  int32_t n_schedule;
+  int32_t precision;       /* ecg_precision */
+  double inner_tol;        /* FP32_REFINED: relative tolerance of each inner solve */
+  int32_t max_outer;       /* FP32_REFINED: maximum refinement steps (>= 1) */
+  int32_t replace_every;   /* FP32_REFINED: recompute r = b - A x in FP64 every this many
+                              inner iterations (0 = never) */
+  int32_t trunc;           /* > 0: A-orthonormalise against the last trunc blocks only
+                              (truncated SRE-CG2, Section 3); 0 = all stored blocks */
+  int64_t q_budget_bytes;  /* bytes of workspace reserved for stored blocks; 0 = room for
+                              kmax blocks.  When full, the oldest block is dropped
+                              (truncation to the blocks that fit). */
+  double deflate_tol;      /* drop a column whose Cholesky pivot <= deflate_tol times its
+                              diagonal entry; < 0 disables deflation (then a non-positive
+                              pivot is ECG_EBREAKDOWN) */
+  int32_t precond;         /* ecg_precond_kind */
+  const ecg_precond* M;    /* used when precond == ECG_PRECOND_SPLIT */
+} ecg_options;
+
+typedef struct {
+  int32_t iters;            /* completed block iterations (all inner iterations summed
+                               for FP32_REFINED) */
+  int32_t n_switch;         /* number of halvings */
+  int32_t switch_iters[8];  /* iteration k at which each halved block was formed */
+  int32_t t_final;          /* block width at the end */
+  int32_t outer_iters;      /* refinement steps (1 for FP64) */
+  int32_t deflated_cols;    /* columns dropped by deflation */
+  int32_t trunc_used;       /* blocks A-orthonormalised against at most (0 = all) */
+  int64_t vectors_stored;   /* sum of the widths of all blocks created (the paper's mem) */
+  double relres_recursive;  /* ||r_k|| / ||r_0|| of the recursion */
+  double relres_true;       /* ||b - A x|| / ||b||, recomputed in FP64 at the end */
+  double seconds;           /* wall time of the solve, host clock */
+  int32_t status;           /* ecg_status of the solve */
+} ecg_report;
+
+/* Fill *o with defaults: tol 1e-8, kmax 20000, no reduction, switch_tol 1e-5, t_min 1,
+ * min_gap 1, FP64, inner_tol 1e-4, max_outer 20, replace_every 0, trunc 0,
+ * q_budget_bytes 0, deflate_tol 1e-14, no preconditioner. */
+ecg_status ecg_options_default(ecg_options* o);
+
+/* Sparse SPD matrix A (n x n) in CSR form, copied to the device.
+ * rowptr: int64[n+1], colind: int32[nnz] (each row sorted ascending, entries in [0,n)),
+ * vals: double[nnz].  on_device != 0: the three arrays are device pointers, else host.
+ * nnz must be < 2^31.  The matrix must be symmetric; this is not checked. */
+ecg_status ecg_operator_create_csr(int64_t n, int64_t nnz, const int64_t* rowptr,
+                                   const int32_t* colind, const double* vals, int on_device,
+                                   void* hip_stream, ecg_operator** out);
+void ecg_operator_destroy(ecg_operator* A);
+/* n and nnz of an operator (host out-pointers). */
+ecg_status ecg_operator_info(const ecg_operator* A, int64_t* n, int64_t* nnz);
+
+/* Subdomain map (Section 2: disjoint delta_1..delta_t).  part: int32[n] with values in
+ * [0, t), every subdomain non-empty (else ECG_EINVAL).  Halving merges subdomains 2i
+ * and 2i+1 (Section 4): the map after l halvings is part >> l.  1 <= t <= 64. */
+ecg_status ecg_partition_create(int64_t n, int32_t t, const int32_t* part, int on_device,
+                                void* hip_stream, ecg_partition** out);
+void ecg_partition_destroy(ecg_partition* P);
+
+/* Block-Jacobi IC(0) preconditioner on the subdomains of P (Section 5.3): A restricted
+ * to each subdomain (couplings between subdomains dropped) is factored by incomplete
+ * Cholesky with zero fill, L_i L_i^T, in the matrix's own ordering.  The factorisation
+ * runs on the device.  Fails with ECG_EBREAKDOWN if a pivot is not positive. */
+ecg_status ecg_precond_create_bj_ic0(const ecg_operator* A, const ecg_partition* P,
+                                     void* hip_stream, ecg_precond** out);
+
+/* Factorised approximate inverse M^{-1} = G G^T (so L^{-1} = G^T, L^{-T} = G in
+ * eq. (zsre2)).  G is lower triangular in CSR (int64 rowptr, int32 colind, double vals,
+ * each row sorted with the diagonal last), device or host per on_device.  Every
+ * diagonal entry must be positive (checked; ECG_EINVAL otherwise). */
+ecg_status ecg_precond_create_factor(int64_t n, int64_t nnz, const int64_t* rowptr,
+                                     const int32_t* colind, const double* vals, int on_device,
+                                     void* hip_stream, ecg_precond** out);
+void ecg_precond_destroy(ecg_precond* M);
+
+/* Bytes of device workspace ecg_solve needs for this operator, partition and options. */
+ecg_status ecg_workspace_size(const ecg_operator* A, const ecg_partition* P,
+                              const ecg_options* o, size_t* bytes);
+
+/* Solve A x = b.  b: device double[n]; x: device double[n], holds x0 on entry and the
+ * solution on exit.  workspace: device, >= ecg_workspace_size bytes, 256-byte aligned;
+ * its contents on entry are irrelevant.  rep: host, filled on every return that got past
+ * argument checking.  rho_hist: host, nullable, length >= kmax; receives ||r_k|| for
+ * k = 0..iters (FP64 solves only).  Returns ECG_OK, ECG_ENOTCONV or an error. */
+ecg_status ecg_solve(const ecg_operator* A, const ecg_partition* P, const double* b, double* x,
+                     const ecg_options* o, void* workspace, size_t ws_bytes, void* hip_stream,
+                     ecg_report* rep, double* rho_hist);
+
+/* y = A x for one vector (device double[n] each); used for true residuals. */
+ecg_status ecg_spmv(const ecg_operator* A, const double* x, double* y, void* hip_stream);
+
+/* ---- per-kernel timing ----------------------------------------------------------
+ * When enabled, ecg_solve brackets every kernel launch of the classes below with HIP
+ * events on its own stream and accumulates, per class: launches, event-measured
+ * milliseconds, and the algorithmic bytes and flops of those launches (the data the
+ * method must move: each stored column read once per sweep, each block row read or
+ * written once).  Classes:
+ *   0 SpMM Y = A X            bytes nnz*(w+4) + 4(n+1) + 2 w n t
+ *   1 CGS2 Gram partials      bytes w n (m_span + t)        (one launch per span)
+ *   2 CGS2 Gram chunk sums    bytes of the partial sums read and G written
+ *   3 CGS2 update W -= Q G    bytes w n (m_span + 2t)       (one launch per span)
+ *   4 t x t Grams             bytes w n (2t [+1])
+ *   5 t x t factor            bytes 0
+ *   6 H = C R^{-1}            bytes 2 w n t
+ *   7 fused final update      bytes 4 w n t + traffic of x and r
+ *   8 split / preconditioner  bytes as the kernels stream them
+ *   9 residuals and norms     bytes of the vectors read and written
+ * w = bytes per value of the block data (8 FP64, 4 FP32).  Timing adds a little host
+ * overhead per launch; leave it off for wall-clock measurements.  Process-global. */
+#define ECG_NSTAT 10
+typedef struct {
+  int64_t count[ECG_NSTAT];
+  double ms[ECG_NSTAT];
+  double bytes[ECG_NSTAT];
+  double flops[ECG_NSTAT];
+} ecg_kernel_stats;
+
+ecg_status ecg_stats_enable(int on);
+/* Copy the accumulated statistics into *out (host); reset != 0 clears them. */
+ecg_status ecg_stats_read(ecg_kernel_stats* out, int reset);
+
+/* Thread-local message for the last failing call. */
+const char* ecg_last_error(void);
+
+/* ---- building blocks exposed for kernel-level tests (device pointers, FP64) ---- */
+
+/* Y = A X for a row-major n x t block (t in 1..64). */
+ecg_status ecg_debug_spmm(const ecg_operator* A, int32_t t, const double* X, double* Y,
+                          void* hip_stream);
+/* out = [T^t(v)] with the map part >> level: out[i][j] = v[i] if (part[i]>>level) == j. */
+ecg_status ecg_debug_split(const ecg_partition* P, int32_t level, const double* v, double* out,
+                           void* hip_stream);
+/* G = Q^T Y where Q is nb blocks of width wq stored block-major ([nb][n][wq]) and Y is a
+ * row-major n x t block.  G: device double[nb*wq][t]. */
+ecg_status ecg_debug_gram(int64_t n, int32_t nb, int32_t wq, const double* Q, int32_t t,
+                          const double* Y, double* G, void* hip_stream);
+/* W -= Q G (same layouts as ecg_debug_gram; W row-major n x t, updated in place). */
+ecg_status ecg_debug_update(int64_t n, int32_t nb, int32_t wq, const double* Q, int32_t t,
+                            const double* G, double* W, void* hip_stream);
+/* Apply the preconditioner factors to a row-major n x t block: which = 0: Y = L^{-1} X,
+ * which = 1: Y = L^{-T} X. */
+ecg_status ecg_debug_precond_apply(const ecg_precond* M, int32_t which, int32_t t,
+                                   const double* X, double* Y, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ECG_H */

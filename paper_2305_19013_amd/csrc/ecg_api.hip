@@ -1,0 +1,1018 @@
+// Host driver and C ABI of the flexibly enlarged CG solver (see include/ecg.h).
+//
+// The iteration (Section 4.3, Algorithm 3; Algorithm 1 without a switch):
+//   k = 1      : candidate = [T^t(r_0)]                       (split kernel)
+//   switch     : candidate = [T^{t/2}(r_{k-1})] on part >> l  (Section 4.2)
+//   otherwise  : candidate = A W_{k-1}  (= Z_{k-1}, produced by the previous update)
+//   CGS2       : twice  Y = A C, G = Q^T Y, C -= Q G          (A-orthonormalise vs Q)
+//   Pre-CholQR : E = C^T C = R^T R, H = C R^{-1}, Y = A H, S = H^T Y = C'^T C',
+//                u = H^T r                                    (self A-orthonormalisation)
+//   update     : W_k = H C'^{-1} (stored), Z_k = Y C'^{-1}, alpha = C'^{-T} u,
+//                x += H C'^{-1} alpha, r -= Y C'^{-1} alpha, rho = ||r||
+// Split preconditioning (Section 4.5, eq. (zsre2)) only changes the candidate:
+//   L^{-T}[T(L^{-1} r)] at k = 1 / at a switch, L^{-T} L^{-1} Z_{k-1} otherwise.
+// One 24-byte device-to-host copy per iteration carries ||r||^2 and the kept-column counts.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "../../include/ecg.h"
+#include "ecg_internal.h"
+
+using namespace ecg;
+
+struct ecg_operator {
+  DevCsr A;
+  int64_t n = 0, nnz = 0;
+  std::vector<int64_t> rowptr;  // host copy (set-up of preconditioners)
+  std::vector<int32_t> col;
+  std::vector<double> val;
+};
+
+struct ecg_partition {
+  int64_t n = 0;
+  int t = 0;
+  int* part = nullptr;  // device
+  std::vector<int32_t> host;
+};
+
+struct ecg_precond {
+  int kind = 0;  // 0: triangular factor L (block-Jacobi IC(0)); 1: G with M^{-1} = G G^T
+  DevTri tri;
+  DevCsr G, Gt;  // kind 1
+  std::vector<void*> owned;
+};
+
+namespace ecg {
+bool g_stats_on = false;
+}
+
+namespace {
+
+thread_local std::string g_err;
+
+// ------------------------------------------------------------------ kernel timing
+struct PendingStat {
+  int cls;
+  hipEvent_t a, b;
+  double bytes, flops;
+};
+std::vector<hipEvent_t> g_event_pool;
+std::vector<PendingStat> g_pending;
+hipEvent_t g_open = nullptr;
+ecg_kernel_stats g_stats;
+
+hipEvent_t take_event() {
+  if (g_event_pool.empty()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  hipEvent_t e = g_event_pool.back();
+  g_event_pool.pop_back();
+  return e;
+}
+
+// Fold the recorded event pairs into g_stats (the stream has been synchronised).
+void flush_stats() {
+  for (const PendingStat& p : g_pending) {
+    float ms = 0.f;
+    if (p.a && p.b && hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      g_stats.count[p.cls] += 1;
+      g_stats.ms[p.cls] += ms;
+      g_stats.bytes[p.cls] += p.bytes;
+      g_stats.flops[p.cls] += p.flops;
+    }
+    if (p.a) g_event_pool.push_back(p.a);
+    if (p.b) g_event_pool.push_back(p.b);
+  }
+  g_pending.clear();
+}
+
+ecg_status fail(ecg_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIPCHK(expr)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) return fail(ECG_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+int pow2_at_least(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// ------------------------------------------------------------------ workspace plan
+struct Plan {
+  int n = 0, t0 = 0, t0p = 0, elt = 8;
+  long long cap = 0;  // Q slots
+  size_t off_status = 0, off_small_part = 0, off_small_out = 0, off_rinv = 0, off_cinv = 0, off_beta = 0,
+         off_norm_part = 0, off_scalar = 0, off_gram_part = 0, off_G = 0, off_C = 0, off_Y = 0, off_H = 0,
+         off_r = 0, off_r64 = 0, off_d = 0, off_v1 = 0, off_v2 = 0, off_Q = 0, total = 0;
+  size_t gram_part_cap = 0;  // elements of T
+  size_t slot_elems = 0;
+};
+
+ecg_status make_plan(int64_t n, int t, const ecg_options& o, Plan* p) {
+  p->n = (int)n;
+  p->t0 = t;
+  p->t0p = pow2_at_least(t);
+  p->elt = o.precision == ECG_FP32_REFINED ? 4 : 8;
+  const int tp = p->t0p;
+  p->slot_elems = (size_t)n * tp;
+  const size_t slot_bytes = p->slot_elems * p->elt;
+  long long cap;
+  if (o.q_budget_bytes > 0) {
+    cap = (long long)(o.q_budget_bytes / (int64_t)slot_bytes);
+  } else if (o.trunc > 0) {
+    cap = o.trunc;
+  } else {
+    cap = std::max(1, o.kmax - 1);
+  }
+  if (o.trunc > 0) cap = std::min<long long>(cap, o.trunc);
+  if (cap < 1) return fail(ECG_EINVAL, "q_budget_bytes is smaller than one stored block");
+  p->cap = cap;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align256(off + bytes);
+    return at;
+  };
+  const size_t small_len = (size_t)tp * tp + tp;
+  p->off_status = take(sizeof(IterStatus));
+  p->off_small_part = take((size_t)kSmallChunks * small_len * 8);
+  p->off_small_out = take(small_len * 8);
+  p->off_rinv = take((size_t)tp * tp * 8);
+  p->off_cinv = take((size_t)tp * tp * 8);
+  p->off_beta = take((size_t)tp * 8);
+  p->off_norm_part = take(((size_t)n / 4 + 64) * 8);
+  p->off_scalar = take(64 * 8);
+  p->gram_part_cap = (size_t)2048 * tp * tp;
+  p->off_gram_part = take(p->gram_part_cap * p->elt);
+  p->off_G = take((size_t)cap * tp * tp * p->elt);
+  p->off_C = take(slot_bytes);
+  p->off_Y = take(slot_bytes);
+  p->off_H = take(slot_bytes);
+  p->off_r = take((size_t)n * p->elt);
+  p->off_v1 = take((size_t)n * 8);
+  p->off_v2 = take((size_t)n * 8);
+  if (o.precision == ECG_FP32_REFINED) {
+    p->off_r64 = take((size_t)n * 8);
+    p->off_d = take((size_t)n * 8);
+  }
+  p->off_Q = take((size_t)cap * slot_bytes);
+  p->total = off;
+  return ECG_OK;
+}
+
+ecg_status check_options(const ecg_options* o) {
+  if (!o) return fail(ECG_EINVAL, "options is NULL");
+  if (!(o->tol >= 0.0)) return fail(ECG_EINVAL, "tol must be >= 0");
+  if (o->kmax < 1) return fail(ECG_EINVAL, "kmax must be >= 1");
+  if (o->reduce < 0 || o->reduce > 3) return fail(ECG_EINVAL, "unknown reduction rule");
+  if (o->t_min < 1) return fail(ECG_EINVAL, "t_min must be >= 1");
+  if (o->min_gap < 1) return fail(ECG_EINVAL, "min_gap must be >= 1");
+  if (o->reduce == ECG_REDUCE_SCHEDULE && o->n_schedule > 0 && !o->schedule)
+    return fail(ECG_EINVAL, "schedule is NULL");
+  if (o->precision != ECG_FP64 && o->precision != ECG_FP32_REFINED) return fail(ECG_EINVAL, "unknown precision");
+  if (o->precision == ECG_FP32_REFINED && (o->max_outer < 1 || !(o->inner_tol > 0.0)))
+    return fail(ECG_EINVAL, "FP32_REFINED needs max_outer >= 1 and inner_tol > 0");
+  if (o->trunc < 0 || o->q_budget_bytes < 0 || o->replace_every < 0) return fail(ECG_EINVAL, "negative size option");
+  if (o->precond != ECG_PRECOND_NONE && o->precond != ECG_PRECOND_SPLIT) return fail(ECG_EINVAL, "unknown precond");
+  if (o->precond == ECG_PRECOND_SPLIT && !o->M) return fail(ECG_EINVAL, "precond SPLIT needs M");
+  return ECG_OK;
+}
+
+// ------------------------------------------------------------------ stored blocks (ring)
+struct QStore {
+  long long cap = 0;
+  long long count = 0;  // blocks ever stored
+  std::vector<int> width;  // per creation index
+};
+
+template <typename T>
+int build_spans(const QStore& q, int trunc_eff, T* Qbase, size_t slot_elems, std::vector<Span<T>>& spans) {
+  spans.clear();
+  const long long nact = std::min<long long>(q.count, trunc_eff);
+  const long long first = q.count - nact;
+  int goff = 0;
+  for (long long j = first; j < q.count; ++j) {
+    const long long slot = j % q.cap;
+    const int w = q.width[j];
+    if (!spans.empty()) {
+      Span<T>& s = spans.back();
+      const long long prev_slot = (j - 1) % q.cap;
+      if (s.width == w && slot == prev_slot + 1) {
+        s.nblk += 1;
+        goff += w;
+        continue;
+      }
+    }
+    Span<T> s;
+    s.base = Qbase + (size_t)slot * slot_elems;
+    s.stride = (long long)slot_elems;
+    s.nblk = 1;
+    s.width = w;
+    s.goff = goff;
+    spans.push_back(s);
+    goff += w;
+  }
+  return goff;  // m
+}
+
+bool switch_now(const ecg_options& o, int k, double tol1, int t_live, const std::vector<int>& switches) {
+  if (t_live % 2 || t_live / 2 < std::max(o.t_min, 1)) return false;
+  switch (o.reduce) {
+    case ECG_REDUCE_NONE:
+      return false;
+    case ECG_REDUCE_SCHEDULE:
+      for (int i = 0; i < o.n_schedule; ++i)
+        if (o.schedule[i] == k) return true;
+      return false;
+    case ECG_REDUCE_SWITCHTOL_ONCE:
+      return tol1 < o.switch_tol && switches.empty();
+    case ECG_REDUCE_SWITCHTOL_REPEAT:
+      return tol1 < o.switch_tol && (switches.empty() || k - switches.back() >= o.min_gap);
+  }
+  return false;
+}
+
+template <typename T>
+const T* vals(const DevCsr& A);
+template <>
+const double* vals<double>(const DevCsr& A) { return A.val; }
+template <>
+const float* vals<float>(const DevCsr& A) { return A.valf; }
+
+// Y = L^{-1} X (which 0) or L^{-T} X (which 1); for M^{-1} = G G^T: L^{-1} = G^T, L^{-T} = G.
+template <typename T>
+void precond_apply(const ecg_precond* M, int which, int tc, const T* X, T* Y, hipStream_t s) {
+  if (M->kind == 0) {
+    launch_trisolve<T>(M->tri, which, tc, X, Y, s);
+  } else {
+    launch_spmm<T>(which == 0 ? M->Gt : M->G, tc, X, Y, s);
+  }
+}
+
+struct InnerResult {
+  int iters = 0;
+  int deflated = 0;
+  long long mem = 0;
+  std::vector<int> switches;
+  int t_final = 0;
+  double rho0 = 0, rho = 0;
+  ecg_status status = ECG_OK;
+};
+
+// One ECG solve on residual r (in place) accumulating the correction into x.
+// rr0 = ||r||^2 on entry.  base_k offsets the iteration numbers of rho_hist/report.
+template <typename T, typename TX>
+ecg_status ecg_inner(const ecg_operator* Aop, const ecg_partition* P, const ecg_options& o, const Plan& pl,
+                     char* ws, TX* x, T* r, double rr0, double tol, const double* b64_for_replace,
+                     hipStream_t s, InnerResult* res, double* rho_hist) {
+  const DevCsr& A = Aop->A;
+  const int n = pl.n;
+  const ecg_precond* M = (o.precond == ECG_PRECOND_SPLIT) ? o.M : nullptr;
+  IterStatus* st = reinterpret_cast<IterStatus*>(ws + pl.off_status);
+  double* small_part = reinterpret_cast<double*>(ws + pl.off_small_part);
+  double* small_out = reinterpret_cast<double*>(ws + pl.off_small_out);
+  double* Rinv = reinterpret_cast<double*>(ws + pl.off_rinv);
+  double* Cinv = reinterpret_cast<double*>(ws + pl.off_cinv);
+  double* beta = reinterpret_cast<double*>(ws + pl.off_beta);
+  double* norm_part = reinterpret_cast<double*>(ws + pl.off_norm_part);
+  T* gram_part = reinterpret_cast<T*>(ws + pl.off_gram_part);
+  T* G = reinterpret_cast<T*>(ws + pl.off_G);
+  T* Cb = reinterpret_cast<T*>(ws + pl.off_C);
+  T* Yb = reinterpret_cast<T*>(ws + pl.off_Y);
+  T* Hb = reinterpret_cast<T*>(ws + pl.off_H);
+  T* Qbase = reinterpret_cast<T*>(ws + pl.off_Q);
+
+  const long long trunc_eff = (o.trunc > 0) ? std::min<long long>(o.trunc, pl.cap) : pl.cap;
+  QStore q;
+  q.cap = pl.cap;
+  std::vector<Span<T>> spans;
+
+  const double rho0 = std::sqrt(rr0);
+  res->rho0 = rho0;
+  res->rho = rho0;
+  res->t_final = P->t;
+  if (rho_hist) rho_hist[0] = rho0;
+  if (rho0 == 0.0) return ECG_OK;
+  const double tau = (sizeof(T) == 4 && o.deflate_tol >= 0.0) ? std::max(o.deflate_tol, 1e-10) : o.deflate_tol;
+
+  double rho_prev = rho0, tol1 = 1.0;
+  int k = 1, level = 0;
+  int tl = P->t;                 // live width
+  int tc = pow2_at_least(tl);    // padded width of the kernels
+  IterStatus hst;
+  int prev_kept = tl;
+  while (rho_prev > tol * rho0 && k < o.kmax) {
+    // ---- candidate block (cand_live: its columns that are not already known zero)
+    bool from_r = false;
+    if (k == 1) {
+      from_r = true;
+    } else if (switch_now(o, k, tol1, tl, res->switches)) {
+      level += 1;
+      tl /= 2;
+      tc = pow2_at_least(tl);
+      res->switches.push_back(k);
+      from_r = true;
+    }
+    if (from_r) {
+      if (M) {
+        precond_apply<T>(M, 0, 1, r, Yb, s);  // L^{-1} r (n x 1)
+        launch_split_t<T>(n, P->part, level, tc, Yb, Hb, s);
+        precond_apply<T>(M, 1, tc, Hb, Cb, s);
+      } else {
+        launch_split_t<T>(n, P->part, level, tc, r, Cb, s);
+      }
+    } else if (M) {
+      precond_apply<T>(M, 0, tc, Cb, Yb, s);  // Cb holds Z_{k-1} = A W_{k-1}
+      precond_apply<T>(M, 1, tc, Yb, Cb, s);
+    }
+    // ---- CGS2 against the stored blocks
+    const int m = build_spans<T>(q, (int)trunc_eff, Qbase, pl.slot_elems, spans);
+    if (m > 0) {
+      for (int pass = 0; pass < 2; ++pass) {
+        launch_spmm<T>(A, tc, Cb, Yb, s);
+        launch_gram<T>(n, spans.data(), (int)spans.size(), m, tc, Yb, G, gram_part, pl.gram_part_cap, s);
+        launch_update<T>(n, spans.data(), (int)spans.size(), tc, G, Cb, s);
+      }
+    }
+    // ---- Pre-CholQR: Euclidean step
+    HIPCHK(hipMemsetAsync(st, 0, sizeof(IterStatus), s));
+    const double w = sizeof(T);
+    stat_begin(s);
+    launch_small_gram<T>(n, tc, Cb, Cb, nullptr, small_part, small_out, s);
+    stat_end(kStatSmallGram, w * n * 2 * tc, 2.0 * n * tc * tc, s);
+    stat_begin(s);
+    launch_factor(0, tc, tl, small_out, tau, Rinv, nullptr, st, s);
+    stat_end(kStatFactor, 0.0, (double)tc * tc * tc, s);
+    stat_begin(s);
+    launch_times_small<T>(n, tc, Cb, Rinv, Hb, s);
+    stat_end(kStatTimesSmall, w * n * 2 * tc, 2.0 * n * tc * tc, s);
+    // ---- A step, alpha and the fused update
+    launch_spmm<T>(A, tc, Hb, Yb, s);
+    stat_begin(s);
+    launch_small_gram<T>(n, tc, Hb, Yb, r, small_part, small_out, s);
+    stat_end(kStatSmallGram, w * n * (2 * tc + 1), 2.0 * n * tc * (tc + 1), s);
+    stat_begin(s);
+    launch_factor(1, tc, tl, small_out, tau, Cinv, beta, st, s);
+    stat_end(kStatFactor, 0.0, (double)tc * tc * tc, s);
+    T* Wslot = Qbase + (size_t)(q.count % q.cap) * pl.slot_elems;
+    const int nwg = launch_final_update<T, TX>(n, tc, Hb, Yb, Cinv, beta, Wslot, Cb, x, r, norm_part, s);
+    launch_sum(norm_part, nwg, &st->rr, s);
+    HIPCHK(hipMemcpyAsync(&hst, st, sizeof(IterStatus), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipGetLastError());
+    if (g_stats_on) flush_stats();
+    if (hst.breakdown) {
+      res->status = ECG_EBREAKDOWN;
+      g_err = "non-positive pivot in the t x t Cholesky with deflation disabled";
+      break;
+    }
+    if (hst.keep_a == 0) {
+      res->status = ECG_EBREAKDOWN;
+      g_err = "every column of the block was deflated (search space exhausted)";
+      break;
+    }
+    // ---- bookkeeping (block stored in its slot by the update kernel)
+    q.width.push_back(tc);
+    q.count += 1;
+    res->mem += hst.keep_a;
+    // a column dropped once stays zero in A W, so it is counted only where it is lost
+    res->deflated += (from_r ? tl : prev_kept) - hst.keep_a;
+    prev_kept = hst.keep_a;
+    const double rho = std::sqrt(std::max(hst.rr, 0.0));
+    tol1 = std::fabs(rho - rho_prev) / rho0;
+    rho_prev = rho;
+    if (rho_hist) rho_hist[k] = rho;
+    if constexpr (std::is_same<T, float>::value) {
+      // residual replacement: r = b - A x recomputed in FP64 (x accumulates in FP64)
+      if (o.replace_every > 0 && b64_for_replace && k % o.replace_every == 0 &&
+          rho_prev > tol * rho0) {
+        const int g = launch_residual_f(A, b64_for_replace, x, r, norm_part, s);
+        launch_sum(norm_part, g, &st->rr, s);
+        HIPCHK(hipMemcpyAsync(&hst, st, sizeof(IterStatus), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        rho_prev = std::sqrt(std::max(hst.rr, 0.0));
+      }
+    }
+    ++k;
+  }
+  res->iters = k - 1;
+  res->rho = rho_prev;
+  res->t_final = tl;
+  if (res->status == ECG_OK && rho_prev > tol * rho0) res->status = ECG_ENOTCONV;
+  return ECG_OK;
+}
+
+ecg_status device_norm2(const DevCsr& A, const double* b, const double* x, double* tmp, double* part,
+                        double* dscalar, hipStream_t s, double* out) {
+  const int g = launch_residual(A, b, x, tmp, part, s);
+  launch_sum(part, g, dscalar, s);
+  HIPCHK(hipMemcpyAsync(out, dscalar, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return ECG_OK;
+}
+
+template <typename T>
+ecg_status copy_in(T** dst, const T* src, size_t count, int on_device, hipStream_t s) {
+  HIPCHK(hipMalloc(dst, std::max<size_t>(count, 1) * sizeof(T)));
+  if (count) HIPCHK(hipMemcpyAsync(*dst, src, count * sizeof(T), on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+  return ECG_OK;
+}
+
+template <typename T>
+ecg_status to_host(std::vector<T>& dst, const T* src, size_t count, int on_device, hipStream_t s) {
+  dst.resize(count);
+  if (!count) return ECG_OK;
+  if (on_device) {
+    HIPCHK(hipMemcpyAsync(dst.data(), src, count * sizeof(T), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+  } else {
+    std::memcpy(dst.data(), src, count * sizeof(T));
+  }
+  return ECG_OK;
+}
+
+ecg_status check_csr(int64_t n, int64_t nnz, const std::vector<int64_t>& rp, const std::vector<int32_t>& ci) {
+  if (n <= 0 || n > 0x7fffffff) return fail(ECG_EINVAL, "n out of range");
+  if (nnz < 0 || nnz >= 0x7fffffffLL) return fail(ECG_EINVAL, "nnz must be < 2^31");
+  if (rp[0] != 0 || rp[n] != nnz) return fail(ECG_EINVAL, "rowptr must start at 0 and end at nnz");
+  for (int64_t i = 0; i < n; ++i) {
+    if (rp[i + 1] < rp[i]) return fail(ECG_EINVAL, "rowptr not non-decreasing");
+    for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+      if (ci[k] < 0 || ci[k] >= n) return fail(ECG_EINVAL, "column index out of range");
+      if (k > rp[i] && ci[k] <= ci[k - 1]) return fail(ECG_EINVAL, "columns of a row must be strictly increasing");
+    }
+  }
+  return ECG_OK;
+}
+
+// Upload a host CSR (int64 rowptr) as DevCsr with an FP32 copy of the values.
+ecg_status upload_csr(int64_t n, const std::vector<int64_t>& rp, const std::vector<int32_t>& ci,
+                      const std::vector<double>& v, hipStream_t s, DevCsr* out, std::vector<void*>* owned) {
+  std::vector<int> rp32(n + 1);
+  for (int64_t i = 0; i <= n; ++i) rp32[i] = (int)rp[i];
+  const size_t nnz = v.size();
+  out->n = (int)n;
+  out->nnz = (int)nnz;
+  ecg_status st;
+  if ((st = copy_in(&out->rowptr, rp32.data(), rp32.size(), 0, s)) != ECG_OK) return st;
+  if ((st = copy_in(&out->col, ci.data(), nnz, 0, s)) != ECG_OK) return st;
+  if ((st = copy_in(&out->val, v.data(), nnz, 0, s)) != ECG_OK) return st;
+  HIPCHK(hipMalloc(&out->valf, std::max<size_t>(nnz, 1) * sizeof(float)));
+  if (nnz) launch_cast_val((int)nnz, out->val, out->valf, s);
+  HIPCHK(hipStreamSynchronize(s));
+  if (owned) {
+    owned->push_back(out->rowptr);
+    owned->push_back(out->col);
+    owned->push_back(out->val);
+    owned->push_back(out->valf);
+  }
+  return ECG_OK;
+}
+
+void free_csr(DevCsr& A) {
+  (void)hipFree(A.rowptr);
+  (void)hipFree(A.col);
+  (void)hipFree(A.val);
+  (void)hipFree(A.valf);
+  A = DevCsr();
+}
+
+// Transpose of a lower-triangular CSR (diag last) -> upper CSR (diag first); perm[kU] = kL.
+void transpose_csr(int64_t n, const std::vector<int64_t>& rp, const std::vector<int32_t>& ci,
+                   std::vector<int64_t>& rpt, std::vector<int32_t>& cit, std::vector<int>& perm) {
+  const size_t nnz = ci.size();
+  rpt.assign(n + 1, 0);
+  for (size_t k = 0; k < nnz; ++k) rpt[ci[k] + 1]++;
+  for (int64_t i = 0; i < n; ++i) rpt[i + 1] += rpt[i];
+  std::vector<int64_t> pos(rpt.begin(), rpt.end() - 1);
+  cit.resize(nnz);
+  perm.resize(nnz);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+      const int64_t d = pos[ci[k]]++;
+      cit[d] = (int32_t)i;
+      perm[d] = (int)k;
+    }
+}
+
+// Level sets: for each group, rows ordered by level.  deps(i) lists rows that must be
+// solved before row i.  forward: rows processed in increasing order; else decreasing.
+void level_sets(int64_t n, const std::vector<int>& group, int ngroups, const std::vector<int64_t>& rp,
+                const std::vector<int32_t>& ci, bool forward, std::vector<int>& lptr, std::vector<int>& lrows,
+                int* maxlev_out, int maxlev_in = -1) {
+  std::vector<int> lev(n, 0);
+  int maxlev = 0;
+  for (int64_t ii = 0; ii < n; ++ii) {
+    const int64_t i = forward ? ii : n - 1 - ii;
+    int l = 0;
+    for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+      const int j = ci[k];
+      if (j == i) continue;
+      l = std::max(l, lev[j] + 1);
+    }
+    lev[i] = l;
+    maxlev = std::max(maxlev, l + 1);
+  }
+  if (maxlev_in > maxlev) maxlev = maxlev_in;
+  std::vector<int> cnt((size_t)ngroups * maxlev, 0);
+  for (int64_t i = 0; i < n; ++i) cnt[(size_t)group[i] * maxlev + lev[i]]++;
+  lptr.assign((size_t)ngroups * (maxlev + 1), 0);
+  std::vector<int> start((size_t)ngroups * maxlev);
+  int acc = 0;
+  for (int g = 0; g < ngroups; ++g) {
+    for (int l = 0; l < maxlev; ++l) {
+      lptr[(size_t)g * (maxlev + 1) + l] = acc;
+      start[(size_t)g * maxlev + l] = acc;
+      acc += cnt[(size_t)g * maxlev + l];
+    }
+    lptr[(size_t)g * (maxlev + 1) + maxlev] = acc;
+  }
+  lrows.resize(n);
+  for (int64_t i = 0; i < n; ++i) lrows[start[(size_t)group[i] * maxlev + lev[i]]++] = (int)i;
+  *maxlev_out = maxlev;
+}
+
+ecg_status make_tri(int64_t n, const std::vector<int>& group, int ngroups, const std::vector<int64_t>& rpL,
+                    const std::vector<int32_t>& ciL, const std::vector<double>& vL, hipStream_t s, ecg_precond* M,
+                    std::vector<int>* permU_out) {
+  std::vector<int64_t> rpU;
+  std::vector<int32_t> ciU;
+  std::vector<int> perm;
+  transpose_csr(n, rpL, ciL, rpU, ciU, perm);
+  std::vector<double> vU(vL.size());
+  for (size_t k = 0; k < vU.size(); ++k) vU[k] = vL[perm[k]];
+  ecg_status st;
+  if ((st = upload_csr(n, rpL, ciL, vL, s, &M->tri.L, nullptr)) != ECG_OK) return st;
+  if ((st = upload_csr(n, rpU, ciU, vU, s, &M->tri.U, nullptr)) != ECG_OK) return st;
+  std::vector<int> lpL, lrL, lpU, lrU;
+  int mlL = 0, mlU = 0;
+  level_sets(n, group, ngroups, rpL, ciL, true, lpL, lrL, &mlL);
+  level_sets(n, group, ngroups, rpU, ciU, false, lpU, lrU, &mlU);
+  // both solves use the same level count so one field describes them
+  const int ml = std::max(mlL, mlU);
+  if (mlL != ml) level_sets(n, group, ngroups, rpL, ciL, true, lpL, lrL, &mlL, ml);
+  if (mlU != ml) level_sets(n, group, ngroups, rpU, ciU, false, lpU, lrU, &mlU, ml);
+  M->tri.ngroups = ngroups;
+  M->tri.maxlev = ml;
+  if ((st = copy_in(&M->tri.lvl_ptr_L, lpL.data(), lpL.size(), 0, s)) != ECG_OK) return st;
+  if ((st = copy_in(&M->tri.lvl_rows_L, lrL.data(), lrL.size(), 0, s)) != ECG_OK) return st;
+  if ((st = copy_in(&M->tri.lvl_ptr_U, lpU.data(), lpU.size(), 0, s)) != ECG_OK) return st;
+  if ((st = copy_in(&M->tri.lvl_rows_U, lrU.data(), lrU.size(), 0, s)) != ECG_OK) return st;
+  HIPCHK(hipStreamSynchronize(s));
+  if (permU_out) *permU_out = perm;
+  return ECG_OK;
+}
+
+}  // namespace
+
+void ecg::stat_begin(hipStream_t s) {
+  if (!g_stats_on) return;
+  g_open = take_event();
+  if (g_open) (void)hipEventRecord(g_open, s);
+}
+
+void ecg::stat_end(int cls, double bytes, double flops, hipStream_t s) {
+  if (!g_stats_on) return;
+  hipEvent_t e = take_event();
+  if (e) (void)hipEventRecord(e, s);
+  g_pending.push_back(PendingStat{cls, g_open, e, bytes, flops});
+  g_open = nullptr;
+}
+
+// ====================================================================== C ABI
+extern "C" {
+
+ecg_status ecg_stats_enable(int on) {
+  g_stats_on = on != 0;
+  return ECG_OK;
+}
+
+ecg_status ecg_stats_read(ecg_kernel_stats* out, int reset) {
+  if (!out) return fail(ECG_EINVAL, "NULL argument");
+  flush_stats();
+  *out = g_stats;
+  if (reset) std::memset(&g_stats, 0, sizeof(g_stats));
+  return ECG_OK;
+}
+
+const char* ecg_last_error(void) { return g_err.c_str(); }
+
+ecg_status ecg_options_default(ecg_options* o) {
+  if (!o) return fail(ECG_EINVAL, "options is NULL");
+  std::memset(o, 0, sizeof(*o));
+  o->tol = 1e-8;
+  o->kmax = 20000;
+  o->reduce = ECG_REDUCE_NONE;
+  o->switch_tol = 1e-5;
+  o->t_min = 1;
+  o->min_gap = 1;
+  o->precision = ECG_FP64;
+  o->inner_tol = 1e-4;
+  o->max_outer = 20;
+  o->deflate_tol = 1e-14;
+  o->precond = ECG_PRECOND_NONE;
+  return ECG_OK;
+}
+
+ecg_status ecg_operator_create_csr(int64_t n, int64_t nnz, const int64_t* rowptr, const int32_t* colind,
+                                   const double* vals, int on_device, void* hip_stream, ecg_operator** out) {
+  if (!out || !rowptr || (nnz > 0 && (!colind || !vals))) return fail(ECG_EINVAL, "NULL argument");
+  if (n <= 0 || n > 0x7fffffff) return fail(ECG_EINVAL, "n out of range");
+  if (nnz < 0 || nnz >= 0x7fffffffLL) return fail(ECG_EINVAL, "nnz must be < 2^31");
+  hipStream_t s = (hipStream_t)hip_stream;
+  auto* op = new ecg_operator();
+  ecg_status st;
+  if ((st = to_host(op->rowptr, rowptr, (size_t)n + 1, on_device, s)) != ECG_OK ||
+      (st = to_host(op->col, colind, (size_t)nnz, on_device, s)) != ECG_OK ||
+      (st = to_host(op->val, vals, (size_t)nnz, on_device, s)) != ECG_OK ||
+      (st = check_csr(n, nnz, op->rowptr, op->col)) != ECG_OK ||
+      (st = upload_csr(n, op->rowptr, op->col, op->val, s, &op->A, nullptr)) != ECG_OK) {
+    free_csr(op->A);
+    delete op;
+    return st;
+  }
+  op->n = n;
+  op->nnz = nnz;
+  *out = op;
+  return ECG_OK;
+}
+
+void ecg_operator_destroy(ecg_operator* A) {
+  if (!A) return;
+  free_csr(A->A);
+  delete A;
+}
+
+ecg_status ecg_operator_info(const ecg_operator* A, int64_t* n, int64_t* nnz) {
+  if (!A) return fail(ECG_EINVAL, "NULL operator");
+  if (n) *n = A->n;
+  if (nnz) *nnz = A->nnz;
+  return ECG_OK;
+}
+
+ecg_status ecg_partition_create(int64_t n, int32_t t, const int32_t* part, int on_device, void* hip_stream,
+                                ecg_partition** out) {
+  if (!out || !part) return fail(ECG_EINVAL, "NULL argument");
+  if (n <= 0 || n > 0x7fffffff) return fail(ECG_EINVAL, "n out of range");
+  if (t < 1 || t > kMaxT) return fail(ECG_EINVAL, "t must be in [1, 64]");
+  hipStream_t s = (hipStream_t)hip_stream;
+  auto* P = new ecg_partition();
+  ecg_status st = to_host(P->host, part, (size_t)n, on_device, s);
+  if (st != ECG_OK) {
+    delete P;
+    return st;
+  }
+  std::vector<int64_t> cnt(t, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    const int p = P->host[i];
+    if (p < 0 || p >= t) {
+      delete P;
+      return fail(ECG_EINVAL, "part[i] outside [0, t)");
+    }
+    cnt[p]++;
+  }
+  for (int j = 0; j < t; ++j)
+    if (cnt[j] == 0) {
+      delete P;
+      return fail(ECG_EINVAL, "empty subdomain " + std::to_string(j));
+    }
+  if ((st = copy_in(&P->part, P->host.data(), (size_t)n, 0, s)) != ECG_OK) {
+    delete P;
+    return st;
+  }
+  if (hipStreamSynchronize(s) != hipSuccess) {
+    (void)hipFree(P->part);
+    delete P;
+    return fail(ECG_EHIP, "partition upload failed");
+  }
+  P->n = n;
+  P->t = t;
+  *out = P;
+  return ECG_OK;
+}
+
+void ecg_partition_destroy(ecg_partition* P) {
+  if (!P) return;
+  (void)hipFree(P->part);
+  delete P;
+}
+
+ecg_status ecg_precond_create_bj_ic0(const ecg_operator* A, const ecg_partition* P, void* hip_stream,
+                                     ecg_precond** out) {
+  if (!A || !P || !out) return fail(ECG_EINVAL, "NULL argument");
+  if (A->n != P->n) return fail(ECG_EINVAL, "operator and partition sizes differ");
+  hipStream_t s = (hipStream_t)hip_stream;
+  const int64_t n = A->n;
+  // pattern of L: lower triangle of A restricted to each subdomain, diagonal last
+  std::vector<int64_t> rp(n + 1, 0);
+  std::vector<int32_t> ci;
+  std::vector<int> apos;
+  for (int64_t i = 0; i < n; ++i) {
+    bool has_diag = false;
+    for (int64_t k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k) {
+      const int j = A->col[k];
+      if (j > i || P->host[j] != P->host[i]) continue;
+      if (j == i) has_diag = true;
+      ci.push_back(j);
+      apos.push_back((int)k);
+    }
+    if (!has_diag) return fail(ECG_EINVAL, "matrix has a missing diagonal entry");
+    rp[i + 1] = (int64_t)ci.size();
+  }
+  std::vector<double> v(ci.size(), 0.0);
+  auto* M = new ecg_precond();
+  M->kind = 0;
+  std::vector<int> group(P->host.begin(), P->host.end());
+  std::vector<int> permU;
+  ecg_status st = make_tri(n, group, P->t, rp, ci, v, s, M, &permU);
+  int* d_apos = nullptr;
+  int* d_fail = nullptr;
+  int* d_perm = nullptr;
+  if (st == ECG_OK) st = copy_in(&d_apos, apos.data(), apos.size(), 0, s);
+  if (st == ECG_OK) st = copy_in(&d_perm, permU.data(), permU.size(), 0, s);
+  if (st == ECG_OK && hipMalloc(&d_fail, sizeof(int)) != hipSuccess) st = fail(ECG_EHIP, "hipMalloc failed");
+  int hfail = 0;
+  if (st == ECG_OK) {
+    (void)hipMemsetAsync(d_fail, 0, sizeof(int), s);
+    launch_ic0(A->A, M->tri, d_apos, d_fail, s);
+    launch_gather((int)ci.size(), M->tri.L.val, d_perm, M->tri.U.val, s);
+    launch_cast_val((int)ci.size(), M->tri.L.val, M->tri.L.valf, s);
+    launch_cast_val((int)ci.size(), M->tri.U.val, M->tri.U.valf, s);
+    if (hipMemcpyAsync(&hfail, d_fail, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      st = fail(ECG_EHIP, std::string("IC(0) factorisation: ") + hipGetErrorString(hipGetLastError()));
+  }
+  (void)hipFree(d_apos);
+  (void)hipFree(d_fail);
+  (void)hipFree(d_perm);
+  if (st == ECG_OK && hfail) st = fail(ECG_EBREAKDOWN, "IC(0) pivot not positive");
+  if (st != ECG_OK) {
+    ecg_precond_destroy(M);
+    return st;
+  }
+  *out = M;
+  return ECG_OK;
+}
+
+ecg_status ecg_precond_create_factor(int64_t n, int64_t nnz, const int64_t* rowptr, const int32_t* colind,
+                                     const double* vals, int on_device, void* hip_stream, ecg_precond** out) {
+  if (!out || !rowptr || !colind || !vals) return fail(ECG_EINVAL, "NULL argument");
+  hipStream_t s = (hipStream_t)hip_stream;
+  std::vector<int64_t> rp;
+  std::vector<int32_t> ci;
+  std::vector<double> v;
+  ecg_status st;
+  if ((st = to_host(rp, rowptr, (size_t)n + 1, on_device, s)) != ECG_OK) return st;
+  if ((st = to_host(ci, colind, (size_t)nnz, on_device, s)) != ECG_OK) return st;
+  if ((st = to_host(v, vals, (size_t)nnz, on_device, s)) != ECG_OK) return st;
+  if ((st = check_csr(n, nnz, rp, ci)) != ECG_OK) return st;
+  for (int64_t i = 0; i < n; ++i) {
+    if (rp[i + 1] == rp[i] || ci[rp[i + 1] - 1] != i) return fail(ECG_EINVAL, "G must be lower triangular with the diagonal last");
+    if (!(v[rp[i + 1] - 1] > 0.0)) return fail(ECG_EINVAL, "G has a non-positive diagonal entry");
+  }
+  std::vector<int64_t> rpt;
+  std::vector<int32_t> cit;
+  std::vector<int> perm;
+  transpose_csr(n, rp, ci, rpt, cit, perm);
+  std::vector<double> vt(v.size());
+  for (size_t k = 0; k < vt.size(); ++k) vt[k] = v[perm[k]];
+  auto* M = new ecg_precond();
+  M->kind = 1;
+  if ((st = upload_csr(n, rp, ci, v, s, &M->G, nullptr)) != ECG_OK ||
+      (st = upload_csr(n, rpt, cit, vt, s, &M->Gt, nullptr)) != ECG_OK) {
+    ecg_precond_destroy(M);
+    return st;
+  }
+  *out = M;
+  return ECG_OK;
+}
+
+void ecg_precond_destroy(ecg_precond* M) {
+  if (!M) return;
+  free_csr(M->tri.L);
+  free_csr(M->tri.U);
+  (void)hipFree(M->tri.lvl_ptr_L);
+  (void)hipFree(M->tri.lvl_rows_L);
+  (void)hipFree(M->tri.lvl_ptr_U);
+  (void)hipFree(M->tri.lvl_rows_U);
+  free_csr(M->G);
+  free_csr(M->Gt);
+  delete M;
+}
+
+ecg_status ecg_workspace_size(const ecg_operator* A, const ecg_partition* P, const ecg_options* o, size_t* bytes) {
+  if (!A || !P || !bytes) return fail(ECG_EINVAL, "NULL argument");
+  ecg_status st = check_options(o);
+  if (st != ECG_OK) return st;
+  if (A->n != P->n) return fail(ECG_EINVAL, "operator and partition sizes differ");
+  Plan pl;
+  if ((st = make_plan(A->n, P->t, *o, &pl)) != ECG_OK) return st;
+  *bytes = pl.total;
+  return ECG_OK;
+}
+
+ecg_status ecg_spmv(const ecg_operator* A, const double* x, double* y, void* hip_stream) {
+  if (!A || !x || !y) return fail(ECG_EINVAL, "NULL argument");
+  hipStream_t s = (hipStream_t)hip_stream;
+  launch_spmv(A->A, x, y, s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  return ECG_OK;
+}
+
+ecg_status ecg_solve(const ecg_operator* A, const ecg_partition* P, const double* b, double* x, const ecg_options* o,
+                     void* workspace, size_t ws_bytes, void* hip_stream, ecg_report* rep, double* rho_hist) {
+  if (!A || !P || !b || !x || !workspace || !rep) return fail(ECG_EINVAL, "NULL argument");
+  ecg_status st = check_options(o);
+  if (st != ECG_OK) return st;
+  if (A->n != P->n) return fail(ECG_EINVAL, "operator and partition sizes differ");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(ECG_EINVAL, "workspace must be 256-byte aligned");
+  if (o->precond == ECG_PRECOND_SPLIT && o->M->kind == 1 && o->M->G.n != A->n)
+    return fail(ECG_EINVAL, "preconditioner size differs from the operator");
+  if (o->precond == ECG_PRECOND_SPLIT && o->M->kind == 0 && o->M->tri.L.n != A->n)
+    return fail(ECG_EINVAL, "preconditioner size differs from the operator");
+  Plan pl;
+  if ((st = make_plan(A->n, P->t, *o, &pl)) != ECG_OK) return st;
+  if (ws_bytes < pl.total) return fail(ECG_ENOMEM, "workspace too small: need " + std::to_string(pl.total) + " bytes");
+  hipStream_t s = (hipStream_t)hip_stream;
+  char* ws = static_cast<char*>(workspace);
+  std::memset(rep, 0, sizeof(*rep));
+  const auto t_start = std::chrono::steady_clock::now();
+  double* norm_part = reinterpret_cast<double*>(ws + pl.off_norm_part);
+  double* dscal = reinterpret_cast<double*>(ws + pl.off_scalar);
+  const int n = pl.n;
+  InnerResult tot;
+  double bnorm2 = 0.0;
+  {
+    // ||b||^2 via the residual kernel on a zero vector held in the H buffer
+    double* zero = reinterpret_cast<double*>(ws + pl.off_v1);
+    double* tmp = reinterpret_cast<double*>(ws + pl.off_v2);
+    HIPCHK(hipMemsetAsync(zero, 0, (size_t)n * 8, s));
+    if ((st = device_norm2(A->A, b, zero, tmp, norm_part, dscal, s, &bnorm2)) != ECG_OK) return st;
+  }
+  if (!std::isfinite(bnorm2)) return fail(ECG_EINVAL, "b contains NaN or Inf");
+  ecg_status final = ECG_OK;
+  int outer = 0;
+  if (o->precision == ECG_FP64) {
+    double* r = reinterpret_cast<double*>(ws + pl.off_r);
+    const int g = launch_residual(A->A, b, x, r, norm_part, s);
+    launch_sum(norm_part, g, dscal, s);
+    double rr0 = 0;
+    HIPCHK(hipMemcpyAsync(&rr0, dscal, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (!std::isfinite(rr0)) return fail(ECG_EINVAL, "initial residual is not finite (NaN in x0?)");
+    st = ecg_inner<double, double>(A, P, *o, pl, ws, x, r, rr0, o->tol, nullptr, s, &tot, rho_hist);
+    if (st != ECG_OK) return st;
+    final = tot.status;
+    outer = 1;
+    rep->relres_recursive = tot.rho0 > 0 ? tot.rho / tot.rho0 : 0.0;
+  } else {
+    double* r64 = reinterpret_cast<double*>(ws + pl.off_r64);
+    double* d = reinterpret_cast<double*>(ws + pl.off_d);
+    float* rf = reinterpret_cast<float*>(ws + pl.off_r);
+    double rr = 0;
+    int g = launch_residual(A->A, b, x, r64, norm_part, s);
+    launch_sum(norm_part, g, dscal, s);
+    HIPCHK(hipMemcpyAsync(&rr, dscal, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (!std::isfinite(rr)) return fail(ECG_EINVAL, "initial residual is not finite (NaN in x0?)");
+    const double rho0 = std::sqrt(rr);
+    tot.rho0 = rho0;
+    final = ECG_ENOTCONV;
+    while (outer < o->max_outer) {
+      if (std::sqrt(rr) <= o->tol * rho0) {
+        final = ECG_OK;
+        break;
+      }
+      HIPCHK(hipMemsetAsync(d, 0, (size_t)n * 8, s));
+      launch_cast_d2f(n, r64, rf, s);
+      InnerResult ir;
+      // the inner tolerance is relative to the inner initial residual, but never asks for
+      // more than the outer target
+      const double itol = std::max(o->inner_tol, o->tol * rho0 / std::sqrt(rr) * 0.5);
+      st = ecg_inner<float, double>(A, P, *o, pl, ws, d, rf, rr, itol, r64, s, &ir, nullptr);
+      if (st != ECG_OK) return st;
+      tot.iters += ir.iters;
+      tot.mem += ir.mem;
+      tot.deflated += ir.deflated;
+      for (int sw : ir.switches) tot.switches.push_back(sw);
+      tot.t_final = ir.t_final;
+      ++outer;
+      launch_axpy_d(n, d, x, s);  // x += d in FP64, then the true FP64 residual below
+      if (ir.status == ECG_EBREAKDOWN && ir.iters == 0) {
+        final = ECG_EBREAKDOWN;
+        break;
+      }
+      g = launch_residual(A->A, b, x, r64, norm_part, s);
+      launch_sum(norm_part, g, dscal, s);
+      HIPCHK(hipMemcpyAsync(&rr, dscal, 8, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      tot.rho = std::sqrt(rr);
+    }
+    if (final != ECG_EBREAKDOWN && std::sqrt(rr) <= o->tol * rho0) final = ECG_OK;
+    rep->relres_recursive = rho0 > 0 ? std::sqrt(rr) / rho0 : 0.0;
+  }
+  // true residual in FP64
+  {
+    double* tmp = reinterpret_cast<double*>(ws + pl.off_v2);
+    double rr = 0;
+    if ((st = device_norm2(A->A, b, x, tmp, norm_part, dscal, s, &rr)) != ECG_OK) return st;
+    rep->relres_true = bnorm2 > 0 ? std::sqrt(rr / bnorm2) : 0.0;
+  }
+  HIPCHK(hipGetLastError());
+  const auto t_end = std::chrono::steady_clock::now();
+  rep->iters = tot.iters;
+  rep->n_switch = (int)tot.switches.size();
+  for (int i = 0; i < (int)tot.switches.size() && i < 8; ++i) rep->switch_iters[i] = tot.switches[i];
+  rep->t_final = tot.t_final;
+  rep->outer_iters = outer;
+  rep->deflated_cols = tot.deflated;
+  rep->trunc_used = (o->trunc > 0 || pl.cap < o->kmax - 1) ? (int)std::min<long long>(pl.cap, o->trunc > 0 ? o->trunc : pl.cap) : 0;
+  rep->vectors_stored = tot.mem;
+  rep->seconds = std::chrono::duration<double>(t_end - t_start).count();
+  rep->status = final;
+  if (final == ECG_EBREAKDOWN) return ECG_EBREAKDOWN;
+  return final;
+}
+
+// ---------------------------------------------------------------- debug entry points
+ecg_status ecg_debug_spmm(const ecg_operator* A, int32_t t, const double* X, double* Y, void* hip_stream) {
+  if (!A || !X || !Y) return fail(ECG_EINVAL, "NULL argument");
+  if (t < 1 || t > 64 || (t & (t - 1))) return fail(ECG_EINVAL, "t must be a power of two in [1, 64]");
+  hipStream_t s = (hipStream_t)hip_stream;
+  launch_spmm<double>(A->A, t, X, Y, s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  return ECG_OK;
+}
+
+ecg_status ecg_debug_split(const ecg_partition* P, int32_t level, const double* v, double* out, void* hip_stream) {
+  if (!P || !v || !out) return fail(ECG_EINVAL, "NULL argument");
+  if (level < 0 || level > 6) return fail(ECG_EINVAL, "level out of range");
+  const int t = (P->t + (1 << level) - 1) >> level;
+  const int tc = pow2_at_least(t);
+  hipStream_t s = (hipStream_t)hip_stream;
+  launch_split<double>((int)P->n, P->part, level, tc, v, out, s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  return ECG_OK;
+}
+
+static bool pow2_le64(int v) { return v >= 1 && v <= 64 && !(v & (v - 1)); }
+
+ecg_status ecg_debug_gram(int64_t n, int32_t nb, int32_t wq, const double* Q, int32_t t, const double* Y, double* G,
+                          void* hip_stream) {
+  if (!Q || !Y || !G || n <= 0 || nb < 1 || !pow2_le64(wq) || !pow2_le64(t)) return fail(ECG_EINVAL, "bad argument");
+  hipStream_t s = (hipStream_t)hip_stream;
+  Span<double> sp{Q, (long long)n * wq, nb, wq, 0};
+  const int m = nb * wq;
+  const size_t cap = (size_t)2048 * 64 * 64;
+  double* part = nullptr;
+  HIPCHK(hipMalloc(&part, cap * sizeof(double)));
+  launch_gram<double>((int)n, &sp, 1, m, t, Y, G, part, cap, s);
+  hipError_t e = hipStreamSynchronize(s);
+  (void)hipFree(part);
+  if (e != hipSuccess) return fail(ECG_EHIP, hipGetErrorString(e));
+  return ECG_OK;
+}
+
+ecg_status ecg_debug_update(int64_t n, int32_t nb, int32_t wq, const double* Q, int32_t t, const double* G, double* W,
+                            void* hip_stream) {
+  if (!Q || !W || !G || n <= 0 || nb < 1 || !pow2_le64(wq) || !pow2_le64(t)) return fail(ECG_EINVAL, "bad argument");
+  hipStream_t s = (hipStream_t)hip_stream;
+  Span<double> sp{Q, (long long)n * wq, nb, wq, 0};
+  launch_update<double>((int)n, &sp, 1, t, G, W, s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  return ECG_OK;
+}
+
+ecg_status ecg_debug_precond_apply(const ecg_precond* M, int32_t which, int32_t t, const double* X, double* Y,
+                                   void* hip_stream) {
+  if (!M || !X || !Y || (which != 0 && which != 1) || !pow2_le64(t)) return fail(ECG_EINVAL, "bad argument");
+  hipStream_t s = (hipStream_t)hip_stream;
+  precond_apply<double>(M, which, t, X, Y, s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  return ECG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,142 @@
+// Internal declarations shared by the kernel and driver translation units.
+// Not part of the public ABI (include/ecg.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace ecg {
+
+constexpr int kBlock = 256;      // threads per workgroup for streaming kernels
+constexpr int kMaxT = 64;        // widest block (t x t factor runs in one workgroup)
+constexpr int kSmallChunks = 512;  // partial sums of the t x t Grams and norms
+
+// Device copy of a sparse matrix in CSR form (int32 row pointers).
+struct DevCsr {
+  int n = 0;
+  int nnz = 0;
+  int* rowptr = nullptr;
+  int* col = nullptr;
+  double* val = nullptr;
+  float* valf = nullptr;  // FP32 copy of val
+};
+
+// One contiguous run of stored blocks of equal width: block j of the span starts at
+// base + j * stride (elements); its Gram rows start at goff + j * width.
+template <typename T>
+struct Span {
+  const T* base;
+  long long stride;
+  int nblk;
+  int width;
+  int goff;
+};
+
+// Per-iteration values read back by the host (one small D2H copy per iteration).
+struct IterStatus {
+  double rr;          // ||r||^2 after the update
+  int keep_e;         // columns kept by the Euclidean QR step
+  int keep_a;         // columns kept by the A-step
+  int breakdown;      // non-positive pivot with deflation disabled
+  int pad;
+};
+
+// ------------------------------------------------------------------ kernel timing
+// Classes as documented for ecg_kernel_stats in include/ecg.h.
+enum StatClass {
+  kStatSpmm = 0, kStatGram = 1, kStatGramReduce = 2, kStatUpdate = 3, kStatSmallGram = 4,
+  kStatFactor = 5, kStatTimesSmall = 6, kStatFinal = 7, kStatSplit = 8, kStatVector = 9, kNumStat = 10
+};
+extern bool g_stats_on;
+// Record an event before a launch / after it (no-ops unless timing is enabled).
+void stat_begin(hipStream_t s);
+void stat_end(int cls, double bytes, double flops, hipStream_t s);
+
+// ------------------------------------------------------------------ launchers
+// All launchers enqueue on `s` and do not synchronise.
+
+// y = b - A x (FP64); per-workgroup partial sums of y_i^2 into part[grid]; returns grid.
+int launch_residual(const DevCsr& A, const double* b, const double* x, double* y, double* part,
+                    hipStream_t s);
+// y = A x (FP64 vector).
+void launch_spmv(const DevCsr& A, const double* x, double* y, hipStream_t s);
+// out = sum of part[0..m) in a fixed order (single workgroup); out is device double.
+void launch_sum(const double* part, int m, double* out, hipStream_t s);
+
+// Y = A X for row-major n x tc blocks.
+template <typename T>
+void launch_spmm(const DevCsr& A, int tc, const T* X, T* Y, hipStream_t s);
+
+// out = [T^{tc}(v)] with the map (part >> level); row-major n x tc (tc >= subdomain count).
+template <typename T>
+void launch_split(int n, const int* part, int level, int tc, const double* v, T* out, hipStream_t s);
+template <typename T>
+void launch_split_t(int n, const int* part, int level, int tc, const T* v, T* out, hipStream_t s);
+
+// CGS2 Gram G = Q^T Y for a list of spans; G is (sum of span widths*nblk) x tc, in T.
+// part_buf must hold nchunks * m * tc values; returns after enqueueing partials + reduce.
+template <typename T>
+void launch_gram(int n, const Span<T>* spans, int nspan, int m, int tc, const T* Y, T* G,
+                 T* part_buf, size_t part_cap, hipStream_t s);
+
+// W -= Q G for the same spans.
+template <typename T>
+void launch_update(int n, const Span<T>* spans, int nspan, int tc, const T* G, T* W, hipStream_t s);
+
+// t x t Grams in FP64: out[0 .. tc*tc) = X^T Y (row a, col b), and if r != nullptr
+// out[tc*tc .. tc*tc+tc) = X^T r.  part must hold kSmallChunks*(tc*tc+tc) doubles.
+template <typename T>
+void launch_small_gram(int n, int tc, const T* X, const T* Y, const T* r, double* part, double* out,
+                       hipStream_t s);
+
+// Cholesky with column deflation of a tc x tc SPD matrix (FP64), single workgroup.
+// mode 0 (Euclidean step): in = E; writes Rinv (tc x tc, upper, zero rows/cols for dropped
+//   columns) and st->keep_e.
+// mode 1 (A step): in = S followed by u (tc); writes Cinv, beta = Cinv Cinv^T u (tc) and
+//   st->keep_a.
+// tc_live: columns >= tc_live are padding (always dropped, not counted as deflated).
+void launch_factor(int mode, int tc, int tc_live, const double* in, double tau, double* inv,
+                   double* beta, IterStatus* st, hipStream_t s);
+
+// out = X M for row-major n x tc X and a tc x tc matrix M (FP64, converted to T).
+template <typename T>
+void launch_times_small(int n, int tc, const T* X, const double* M, T* out, hipStream_t s);
+
+// Final fused update: Wq = H Cinv (stored block), Zn = Y Cinv (next candidate),
+// x += H beta, r -= Y beta, per-workgroup partial sums of r^2 (returns grid size).
+template <typename T, typename TX>
+int launch_final_update(int n, int tc, const T* H, const T* Y, const double* Cinv,
+                        const double* beta, T* Wq, T* Zn, TX* x, T* r, double* part, hipStream_t s);
+
+// Precision conversion helpers.
+void launch_cast_d2f(int n, const double* in, float* out, hipStream_t s);
+void launch_axpy_f2d(int n, const float* d, double* x, hipStream_t s);  // x += d
+void launch_axpy_d(int n, const double* d, double* x, hipStream_t s);    // x += d
+void launch_cast_val(int nnz, const double* in, float* out, hipStream_t s);
+// r = (float)(b - A x) computed in FP64; partial sums of the FP64 residual squared.
+int launch_residual_f(const DevCsr& A, const double* b, const double* x, float* r, double* part,
+                      hipStream_t s);
+
+// ---- block-Jacobi IC(0) and sparse triangular solves -------------------------
+struct DevTri {
+  // Lower factor L (CSR, diagonal last in each row) and L^T (CSR, diagonal first),
+  // rows grouped by independent group (subdomain) and level.
+  DevCsr L, U;
+  int ngroups = 0;
+  int* lvl_ptr_L = nullptr;   // [ngroups*(maxlev+1)] row-list offsets per (group, level)
+  int* lvl_rows_L = nullptr;  // row ids ordered by (group, level)
+  int* lvl_ptr_U = nullptr;
+  int* lvl_rows_U = nullptr;
+  int maxlev = 0;
+};
+// Y = L^{-1} X (which = 0) or Y = L^{-T} X (which = 1) for row-major n x tc blocks.
+template <typename T>
+void launch_trisolve(const DevTri& M, int which, int tc, const T* X, T* Y, hipStream_t s);
+// IC(0) numeric factorisation into M.L.val (pattern already set), FP64; sets *fail.
+void launch_ic0(const DevCsr& A, DevTri& M, const int* diag_pos_A, int* fail, hipStream_t s);
+// Copy L values into U (transpose) using a precomputed permutation U.val[k] = L.val[perm[k]].
+void launch_gather(int nnz, const double* src, const int* perm, double* dst, hipStream_t s);
+
+}  // namespace ecg

@@ -1,0 +1,307 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances: FP64 iterates agree to 1e-10 relative (||x_gpu - x_ora|| <= 1e-10 ||x_ora||),
+recursive residual norms to 1e-10 * rho_0, iteration counts, switch iterations and
+stored-vector counts exactly.  Kernel building blocks agree with NumPy/SciPy products
+to a few ulps of the accumulated magnitudes.
+"""
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import ecg as ora
+from oracle import precond as opre
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible GPU")
+    from paper_2305_19013_amd import ecg
+
+    ecg.lib()  # raises if libecg.so is missing: no fallback
+    return torch, torch.device("cuda:0")
+
+
+def _t(torch, dev, a, dtype=None):
+    a = np.ascontiguousarray(a)
+    return torch.from_numpy(a).to(dev) if dtype is None else torch.from_numpy(a).to(dev, dtype)
+
+
+def _solve(torch, dev, csr, b, part, t, x0=None, **kw):
+    from paper_2305_19013_amd import ecg
+
+    op = ecg.Operator.from_csr(csr)
+    P = ecg.Partition(part, t)
+    bt = _t(torch, dev, b)
+    xt = torch.zeros_like(bt) if x0 is None else _t(torch, dev, x0)
+    hist = kw.pop("rho_hist", False)
+    rep, rh = ecg.solve(op, P, bt, xt, ecg.options(**kw), rho_hist=hist)
+    torch.cuda.synchronize()
+    return rep, xt.cpu().numpy(), rh
+
+
+# ---------------------------------------------------------------- building blocks
+@pytest.mark.parametrize("t", [1, 8, 32, 64])
+def test_spmm_matches_scipy(torch_dev, t):
+    torch, dev = torch_dev
+    from paper_2305_19013_amd import ecg
+
+    p = W.config("jump2d512", scale=8)
+    A = p.A.to_scipy()
+    X = np.random.default_rng(t).standard_normal((p.n, t))
+    op = ecg.Operator.from_csr(p.A)
+    Xt = _t(torch, dev, X)
+    Yt = torch.empty_like(Xt)
+    ecg.debug_spmm(op, t, Xt, Yt)
+    ref = A @ X
+    scale = abs(A) @ np.abs(X)
+    assert np.all(np.abs(Yt.cpu().numpy() - ref) <= 4e-16 * 8 * scale + 1e-300)
+
+
+@pytest.mark.parametrize("level", [0, 1, 2])
+def test_split_is_exact(torch_dev, level):
+    torch, dev = torch_dev
+    from paper_2305_19013_amd import ecg
+
+    p = W.config("jump2d512", scale=8)
+    P = ecg.Partition(p.part, p.t)
+    v = W.rhs_uniform(p.n, 5)
+    tl = p.t >> level
+    out = torch.empty((p.n, tl), dtype=torch.float64, device=dev)
+    ecg.debug_split(P, level, _t(torch, dev, v), out)
+    assert np.array_equal(out.cpu().numpy(), ora.split(v, ora.merged_partition(p.part, level), tl))
+
+
+@pytest.mark.parametrize("n,nb,wq,t", [(4099, 3, 8, 8), (4099, 2, 32, 16), (70001, 5, 32, 32),
+                                       (3000, 1, 64, 64), (1027, 4, 16, 64), (5000, 3, 64, 8)])
+def test_gram_and_update_match_numpy(torch_dev, n, nb, wq, t):
+    torch, dev = torch_dev
+    from paper_2305_19013_amd import ecg
+
+    rng = np.random.default_rng(n + t)
+    Q = rng.standard_normal((nb, n, wq))
+    Y = rng.standard_normal((n, t))
+    Qm = np.concatenate([Q[j] for j in range(nb)], axis=1)  # n x (nb*wq)
+    Qt = _t(torch, dev, Q)
+    Yt = _t(torch, dev, Y)
+    Gt = torch.empty((nb * wq, t), dtype=torch.float64, device=dev)
+    ecg.debug_gram(n, nb, wq, Qt, t, Yt, Gt)
+    G = Gt.cpu().numpy()
+    ref = Qm.T @ Y
+    bound = 1e-15 * np.sqrt(n) * 10 * (np.abs(Qm).T @ np.abs(Y))
+    assert np.all(np.abs(G - ref) <= bound)
+    W0 = rng.standard_normal((n, t))
+    Wt = _t(torch, dev, W0)
+    ecg.debug_update(n, nb, wq, Qt, t, Gt, Wt)
+    refw = W0 - Qm @ G
+    boundw = 1e-15 * nb * wq * 4 * (np.abs(W0) + np.abs(Qm) @ np.abs(G))
+    assert np.all(np.abs(Wt.cpu().numpy() - refw) <= boundw)
+
+
+def test_block_jacobi_ic0_apply_matches_oracle(torch_dev):
+    torch, dev = torch_dev
+    from paper_2305_19013_amd import ecg
+
+    p = W.config("learn2d256", seed=7, scale=4)
+    A = p.A.to_scipy()
+    _, L = opre.bj_ic0_preconditioner(A, p.part)
+    op = ecg.Operator.from_csr(p.A)
+    P = ecg.Partition(p.part, p.t)
+    M = ecg.Precond.bj_ic0(op, P)
+    X = np.random.default_rng(1).standard_normal((p.n, 16))
+    Xt = _t(torch, dev, X)
+    Yt = torch.empty_like(Xt)
+    import scipy.sparse.linalg as spl
+
+    M.apply(0, 16, Xt, Yt)
+    ref = spl.spsolve_triangular(L.tocsr(), X, lower=True)
+    assert np.abs(Yt.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+    M.apply(1, 16, Xt, Yt)
+    ref = spl.spsolve_triangular(L.T.tocsr(), X, lower=False)
+    assert np.abs(Yt.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+# ---------------------------------------------------------------- whole solves
+def _check_iterates(torch, dev, csr, b, part, t, ref, ks, **kw):
+    """GPU solves stopped after k iterations (kmax = k + 1) against oracle iterates."""
+    for k in ks:
+        rep, x, _ = _solve(torch, dev, csr, b, part, t, kmax=k + 1, **kw)
+        assert rep["iters"] == k
+        xo = ref.iterates[k - 1]
+        err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+        assert err <= 1e-10, (k, err)
+
+
+def test_poisson64_parity(torch_dev):
+    """The 64x64 Poisson workload (t = 8, 2x4 boxes, no reduction)."""
+    torch, dev = torch_dev
+    p = W.config("poisson64")
+    A = p.A.to_scipy()
+    ref = ora.flexible_sre_cg2(A, p.b, p.part, p.t, tol=p.tol, record=True)
+    rep, x, rh = _solve(torch, dev, p.A, p.b, p.part, p.t, tol=p.tol, rho_hist=True)
+    assert rep["status"] == "ok"
+    assert rep["iters"] == ref.it and rep["vectors_stored"] == ref.mem
+    assert np.abs(rh - np.array(ref.rho)).max() <= 1e-10 * ref.rho[0]
+    assert np.linalg.norm(x - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
+    assert rep["relres_true"] <= 1.01e-8
+    _check_iterates(torch, dev, p.A, p.b, p.part, p.t, ref, [1, 2, 5, 20, 60], tol=p.tol)
+
+
+def test_poisson64_flexible_switch_parity(torch_dev):
+    torch, dev = torch_dev
+    p = W.config("poisson64")
+    A = p.A.to_scipy()
+    kw = dict(reduce=ora.REDUCE_ONCE, switch_tol=1e-4, t_min=2)
+    ref = ora.flexible_sre_cg2(A, p.b, p.part, p.t, tol=p.tol, record=True, **kw)
+    assert len(ref.switch_iters) == 1
+    rep, x, rh = _solve(torch, dev, p.A, p.b, p.part, p.t, tol=p.tol, rho_hist=True, **kw)
+    assert rep["iters"] == ref.it and rep["switch_iters"] == ref.switch_iters
+    assert rep["vectors_stored"] == ref.mem == ora.memory_formula(p.t, ref.it, ref.sit)
+    assert np.abs(rh - np.array(ref.rho)).max() <= 1e-10 * ref.rho[0]
+    s = ref.switch_iters[0]
+    _check_iterates(torch, dev, p.A, p.b, p.part, p.t, ref, [s - 1, s, s + 3, ref.it], tol=p.tol, **kw)
+
+
+def test_repeated_halving_and_schedule_parity(torch_dev):
+    torch, dev = torch_dev
+    p = W.config("jump3d160", scale=8)  # 20^3 grid, t = 64 from 4x4x4 boxes
+    A = p.A.to_scipy()
+    kw = dict(reduce=ora.REDUCE_SCHEDULE, schedule=[3, 5, 9], t_min=8)
+    ref = ora.flexible_sre_cg2(A, p.b, p.part, p.t, tol=1e-30, kmax=13, record=True, **kw)
+    rep, x, _ = _solve(torch, dev, p.A, p.b, p.part, p.t, tol=1e-30, kmax=13, **kw)
+    assert rep["switch_iters"] == [3, 5, 9] and rep["t_final"] == 8
+    assert rep["iters"] == 12 and rep["vectors_stored"] == ref.mem
+    assert np.linalg.norm(x - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
+
+
+@pytest.mark.parametrize("n,t", [(48, 4), (45, 5), (50, 4), (60, 6)])
+def test_tiny_dense_termination_and_padding(torch_dev, n, t):
+    """Ragged widths (t padded to a power of two inside) and exact termination."""
+    torch, dev = torch_dev
+    A = W.random_spd(n, 30.0, 17)
+    b = W.rhs_uniform(n, 18)
+    part = W.random_partition(n, t, 19)
+    ref = ora.flexible_sre_cg2(A, b, part, t, tol=1e-11, record=True)
+    rep, x, _ = _solve(torch, dev, W.dense_to_csr(A), b, part, t, tol=1e-11)
+    assert rep["iters"] == ref.it == -(-n // t)
+    assert rep["vectors_stored"] == ref.mem == n
+    assert rep["deflated_cols"] == ref.deflated
+    assert np.linalg.norm(x - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
+
+
+def test_deflated_zero_subdomain(torch_dev):
+    torch, dev = torch_dev
+    n, t = 40, 4
+    A = W.random_spd(n, 50.0, 29)
+    b = W.rhs_uniform(n, 30)
+    part = W.random_partition(n, t, 31)
+    b[part == 2] = 0.0
+    ref = ora.flexible_sre_cg2(A, b, part, t, tol=1e-10, record=True)
+    rep, x, _ = _solve(torch, dev, W.dense_to_csr(A), b, part, t, tol=1e-10)
+    assert ref.widths[0] == 3
+    assert rep["iters"] == ref.it and rep["vectors_stored"] == ref.mem and rep["deflated_cols"] == ref.deflated
+    assert np.linalg.norm(x - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
+    rep2, _, _ = _solve(torch, dev, W.dense_to_csr(A), b, part, t, tol=1e-10, deflate_tol=-1.0)
+    assert rep2["status"] == "breakdown"
+
+
+def test_kmax_not_converged(torch_dev):
+    torch, dev = torch_dev
+    p = W.config("poisson64")
+    rep, _, _ = _solve(torch, dev, p.A, p.b, p.part, p.t, kmax=3)
+    assert rep["status"] == "not_converged" and rep["iters"] == 2
+
+
+def test_q_budget_truncation_parity(torch_dev):
+    """A Q budget of 6 blocks = truncated SRE-CG2 with trunc = 6 (Section 3)."""
+    torch, dev = torch_dev
+    p = W.config("poisson64")
+    A = p.A.to_scipy()
+    ref = ora.flexible_sre_cg2(A, p.b, p.part, p.t, tol=p.tol, trunc=6)
+    rep, x, _ = _solve(torch, dev, p.A, p.b, p.part, p.t, tol=p.tol, q_budget_bytes=6 * p.n * 8 * 8)
+    assert rep["iters"] == ref.it
+    assert np.linalg.norm(x - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
+    rep2, x2, _ = _solve(torch, dev, p.A, p.b, p.part, p.t, tol=p.tol, trunc=6)
+    assert rep2["iters"] == ref.it
+    assert np.linalg.norm(x2 - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
+
+
+def test_nonzero_initial_guess(torch_dev):
+    torch, dev = torch_dev
+    p = W.config("poisson64")
+    A = p.A.to_scipy()
+    x0 = W.rhs_uniform(p.n, 77)
+    ref = ora.flexible_sre_cg2(A, p.b, p.part, p.t, x0=x0, tol=p.tol)
+    rep, x, _ = _solve(torch, dev, p.A, p.b, p.part, p.t, x0=x0, tol=p.tol)
+    assert rep["iters"] == ref.it
+    assert np.linalg.norm(x - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
+
+
+def test_block_jacobi_preconditioned_parity(torch_dev):
+    torch, dev = torch_dev
+    from paper_2305_19013_amd import ecg
+
+    p = W.config("learn2d256", seed=11, scale=4)  # 64x64, t = 16
+    A = p.A.to_scipy()
+    pre, _ = opre.bj_ic0_preconditioner(A, p.part)
+    ref = ora.flexible_sre_cg2(A, p.b, p.part, p.t, tol=1e-8, precond=pre, record=True)
+    op = ecg.Operator.from_csr(p.A)
+    P = ecg.Partition(p.part, p.t)
+    M = ecg.Precond.bj_ic0(op, P)
+    bt = _t(torch, dev, p.b)
+    xt = torch.zeros_like(bt)
+    rep, _ = ecg.solve(op, P, bt, xt, ecg.options(tol=1e-8, M=M))
+    assert rep["iters"] == ref.it
+    x = xt.cpu().numpy()
+    assert np.linalg.norm(x - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
+
+
+def test_factor_preconditioned_parity(torch_dev):
+    """M^{-1} = G G^T with G = D^{-1/2} + strictly lower part (a Jacobi-like factor)."""
+    torch, dev = torch_dev
+    import scipy.sparse as sp
+
+    from paper_2305_19013_amd import ecg
+
+    p = W.config("learn2d256", seed=12, scale=4)
+    A = p.A.to_scipy()
+    d = A.diagonal()
+    low = sp.tril(A, -1, format="csr")
+    G = sp.csr_matrix(sp.diags(1.0 / np.sqrt(d)) - 0.3 * sp.diags(1.0 / d) @ low @ sp.diags(1.0 / np.sqrt(d)))
+    G = sp.csr_matrix(sp.tril(G))
+    G.sort_indices()
+    pre = opre.factor_preconditioner(G)
+    ref = ora.flexible_sre_cg2(A, p.b, p.part, p.t, tol=1e-8, precond=pre, reduce=ora.REDUCE_ONCE,
+                               switch_tol=1e-4, t_min=2)
+    M = ecg.Precond.factor(G.indptr, G.indices, G.data)
+    rep, x, _ = _solve(torch, dev, p.A, p.b, p.part, p.t, tol=1e-8, M=M, reduce=ora.REDUCE_ONCE,
+                       switch_tol=1e-4, t_min=2)
+    assert rep["iters"] == ref.it and rep["switch_iters"] == ref.switch_iters
+    assert np.linalg.norm(x - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
+
+
+def test_fp32_refined_reaches_fp64_accuracy(torch_dev):
+    torch, dev = torch_dev
+    p = W.config("poisson64")
+    A = p.A.to_scipy()
+    rep, x, _ = _solve(torch, dev, p.A, p.b, p.part, p.t, tol=1e-8, precision=1, inner_tol=1e-4,
+                       replace_every=25)
+    assert rep["status"] == "ok"
+    assert rep["relres_true"] <= 1e-8
+    assert ora.true_relres(A, p.b, x) <= 1e-8
+    xs = __import__("scipy.sparse.linalg", fromlist=["spsolve"]).spsolve(A.tocsc(), p.b)
+    assert np.linalg.norm(x - xs) <= 1e-6 * np.linalg.norm(xs)
+
+
+def test_determinism_bitwise(torch_dev):
+    torch, dev = torch_dev
+    p = W.config("jump2d512", scale=4)
+    r1, x1, _ = _solve(torch, dev, p.A, p.b, p.part, p.t, kmax=40)
+    r2, x2, _ = _solve(torch, dev, p.A, p.b, p.part, p.t, kmax=40)
+    assert np.array_equal(x1, x2)

@@ -239,3 +239,52 @@ def test_split_preconditioned_equals_run_on_transformed_system():
     for k in range(5):
         xk = Linv.T @ hat.iterates[k]
         assert np.linalg.norm(res.iterates[k] - xk) <= 1e-10 * np.linalg.norm(xk)
+
+
+# ---------------------------------------------------------------- IC(0) block Jacobi (Section 5.3)
+def test_ic0_is_exact_cholesky_without_fill():
+    # a tridiagonal SPD matrix has no fill-in, so IC(0) is its Cholesky factor (LAPACK)
+    import scipy.sparse as sp
+
+    from oracle import precond
+
+    n = 30
+    rng = np.random.default_rng(3)
+    off = -rng.uniform(0.2, 1.0, n - 1)
+    d = np.abs(np.r_[0, off]) + np.abs(np.r_[off, 0]) + rng.uniform(0.1, 1.0, n)
+    A = sp.diags([off, d, off], [-1, 0, 1], format="csr")
+    L = precond.ic0(A).toarray()
+    assert np.allclose(L, np.linalg.cholesky(A.toarray()), rtol=0, atol=1e-13)
+
+
+def test_ic0_matches_a_on_its_pattern():
+    # defining property of IC(0): (L L^T)_ij = a_ij for every (i, j) in the pattern of A
+    from oracle import precond
+
+    p = W.config("learn2d256", seed=3, scale=8)
+    A = p.A.to_scipy()
+    Ab = precond.block_diagonal_part(A, p.part)
+    L = precond.ic0(Ab)
+    LLT = (L @ L.T).tocsr()
+    coo = Ab.tocoo()
+    assert np.abs(np.asarray(LLT[coo.row, coo.col]).ravel() - coo.data).max() <= 1e-12 * np.abs(coo.data).max()
+    # couplings across subdomains are absent from L
+    Lc = L.tocoo()
+    assert np.all(p.part[Lc.row] == p.part[Lc.col])
+
+
+def test_block_jacobi_commutes_with_split():
+    # Section 4.5: for a block-diagonal M on the t subdomains, L^{-T} T(L^{-1} r) = M^{-1} T(r)
+    from oracle import precond
+
+    p = W.config("learn2d256", seed=4, scale=8)
+    A = p.A.to_scipy()
+    pre, _ = precond.bj_ic0_preconditioner(A, p.part)
+    r = W.rhs_uniform(p.n, 9)
+    lhs = pre.linvT(ecg.split(pre.linv(r), p.part, p.t))
+    rhs = pre.minv(ecg.split(r, p.part, p.t))
+    assert np.abs(lhs - rhs).max() <= 1e-12 * np.abs(rhs).max()
+    # also after one halving (merged subdomains are unions of the original blocks)
+    lhs = pre.linvT(ecg.split(pre.linv(r), p.part >> 1, p.t // 2))
+    rhs = pre.minv(ecg.split(r, p.part >> 1, p.t // 2))
+    assert np.abs(lhs - rhs).max() <= 1e-12 * np.abs(rhs).max()
