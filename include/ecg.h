@@ -75,7 +75,8 @@ typedef struct ecg_precond ecg_precond;      /* split preconditioner M = L L^T *
 
 typedef struct {
   double tol;              /* stop when ||r_k|| <= tol * ||r_0|| (recursive residual) */
-  int32_t kmax;            /* loop runs while k < kmax (at most kmax-1 iterations) */
+  int32_t kmax;            /* loop runs while k < kmax (at most kmax-1 iterations); for
+                              FP32_REFINED the budget of all inner iterations together */
   int32_t reduce;          /* ecg_reduce */
   double switch_tol;       /* switchTol of Section 4.2 */
   int32_t t_min;           /* never halve below this width (>= 1) */
@@ -86,12 +87,16 @@ typedef struct {
   double inner_tol;        /* FP32_REFINED: relative tolerance of each inner solve */
   int32_t max_outer;       /* FP32_REFINED: maximum refinement steps (>= 1) */
   int32_t replace_every;   /* FP32_REFINED: recompute r = b - A x in FP64 every this many
-                              inner iterations (0 = never) */
+                              inner iterations (0 = never).  An inner solve whose true
+                              residual falls by less than 10% over four replacements ends
+                              and the next refinement step starts; refinement stops when a
+                              step gains less than 10%. */
   int32_t trunc;           /* > 0: A-orthonormalise against the last trunc blocks only
                               (truncated SRE-CG2, Section 3); 0 = all stored blocks */
   int64_t q_budget_bytes;  /* bytes of workspace reserved for stored blocks; 0 = room for
-                              kmax blocks.  When full, the oldest block is dropped
-                              (truncation to the blocks that fit). */
+                              kmax-1 blocks of width t (or trunc blocks).  Blocks are packed
+                              by their width; when the next one does not fit, the oldest
+                              are dropped (truncation to the blocks that fit). */
   double deflate_tol;      /* drop a column whose Cholesky pivot <= deflate_tol times its
                               diagonal entry; < 0 disables deflation (then a non-positive
                               pivot is ECG_EBREAKDOWN) */
@@ -107,7 +112,8 @@ typedef struct {
   int32_t t_final;          /* block width at the end */
   int32_t outer_iters;      /* refinement steps (1 for FP64) */
   int32_t deflated_cols;    /* columns dropped by deflation */
-  int32_t trunc_used;       /* blocks A-orthonormalised against at most (0 = all) */
+  int32_t trunc_used;       /* the trunc option in force (0 = all stored blocks) */
+  int32_t blocks_dropped;   /* stored blocks evicted because q_budget_bytes was full */
   int64_t vectors_stored;   /* sum of the widths of all blocks created (the paper's mem) */
   double relres_recursive;  /* ||r_k|| / ||r_0|| of the recursion */
   double relres_true;       /* ||b - A x|| / ||b||, recomputed in FP64 at the end */
@@ -199,6 +205,10 @@ typedef struct {
 ecg_status ecg_stats_enable(int on);
 /* Copy the accumulated statistics into *out (host); reset != 0 clears them. */
 ecg_status ecg_stats_read(ecg_kernel_stats* out, int reset);
+
+/* Print "ecg: k=... rho/rho0=... t=... m=... elapsed=..." to stderr every `every`
+ * iterations of ecg_solve (0 = never, the default).  Process-global. */
+ecg_status ecg_progress(int32_t every);
 
 /* Thread-local message for the last failing call. */
 const char* ecg_last_error(void);

@@ -18,7 +18,9 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <deque>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -53,6 +55,7 @@ struct ecg_precond {
 namespace ecg {
 bool g_stats_on = false;
 }
+static int g_progress_every = 0;
 
 namespace {
 
@@ -118,7 +121,7 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 // ------------------------------------------------------------------ workspace plan
 struct Plan {
   int n = 0, t0 = 0, t0p = 0, elt = 8;
-  long long cap = 0;  // Q slots
+  long long cap = 0;  // stored-block arena capacity, in columns of n values
   size_t off_status = 0, off_small_part = 0, off_small_out = 0, off_rinv = 0, off_cinv = 0, off_beta = 0,
          off_norm_part = 0, off_scalar = 0, off_gram_part = 0, off_G = 0, off_C = 0, off_Y = 0, off_H = 0,
          off_r = 0, off_r64 = 0, off_d = 0, off_v1 = 0, off_v2 = 0, off_Q = 0, total = 0;
@@ -134,16 +137,17 @@ ecg_status make_plan(int64_t n, int t, const ecg_options& o, Plan* p) {
   const int tp = p->t0p;
   p->slot_elems = (size_t)n * tp;
   const size_t slot_bytes = p->slot_elems * p->elt;
-  long long cap;
+  const size_t col_bytes = (size_t)n * p->elt;
+  long long cap;  // columns
   if (o.q_budget_bytes > 0) {
-    cap = (long long)(o.q_budget_bytes / (int64_t)slot_bytes);
+    cap = (long long)(o.q_budget_bytes / (int64_t)col_bytes);
   } else if (o.trunc > 0) {
-    cap = o.trunc;
+    cap = (long long)o.trunc * tp;
   } else {
-    cap = std::max(1, o.kmax - 1);
+    cap = (long long)std::max(1, o.kmax - 1) * tp;
   }
-  if (o.trunc > 0) cap = std::min<long long>(cap, o.trunc);
-  if (cap < 1) return fail(ECG_EINVAL, "q_budget_bytes is smaller than one stored block");
+  if (o.trunc > 0) cap = std::min<long long>(cap, (long long)o.trunc * tp);
+  if (cap < tp) return fail(ECG_EINVAL, "q_budget_bytes is smaller than one stored block");
   p->cap = cap;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -153,16 +157,16 @@ ecg_status make_plan(int64_t n, int t, const ecg_options& o, Plan* p) {
   };
   const size_t small_len = (size_t)tp * tp + tp;
   p->off_status = take(sizeof(IterStatus));
-  p->off_small_part = take((size_t)kSmallChunks * small_len * 8);
+  p->off_small_part = take(((size_t)kSmallChunks + 32) * small_len * 8);  // chunks + stage-2 rows
   p->off_small_out = take(small_len * 8);
   p->off_rinv = take((size_t)tp * tp * 8);
   p->off_cinv = take((size_t)tp * tp * 8);
   p->off_beta = take((size_t)tp * 8);
-  p->off_norm_part = take(((size_t)n / 4 + 64) * 8);
+  p->off_norm_part = take(((size_t)n / 4 + 64 + 128) * 8);  // partials + stage-2 slices
   p->off_scalar = take(64 * 8);
-  p->gram_part_cap = (size_t)2048 * tp * tp;
+  p->gram_part_cap = (size_t)1 << 26;  // elements: partial Gram sums of the row chunks
   p->off_gram_part = take(p->gram_part_cap * p->elt);
-  p->off_G = take((size_t)cap * tp * tp * p->elt);
+  p->off_G = take((size_t)cap * tp * p->elt);
   p->off_C = take(slot_bytes);
   p->off_Y = take(slot_bytes);
   p->off_H = take(slot_bytes);
@@ -173,7 +177,7 @@ ecg_status make_plan(int64_t n, int t, const ecg_options& o, Plan* p) {
     p->off_r64 = take((size_t)n * 8);
     p->off_d = take((size_t)n * 8);
   }
-  p->off_Q = take((size_t)cap * slot_bytes);
+  p->off_Q = take((size_t)cap * col_bytes);
   p->total = off;
   return ECG_OK;
 }
@@ -196,39 +200,63 @@ ecg_status check_options(const ecg_options* o) {
   return ECG_OK;
 }
 
-// ------------------------------------------------------------------ stored blocks (ring)
+// ------------------------------------------------------------------ stored blocks (arena)
+// The stored blocks live in a circular arena of `cap` columns (n values each).  A block
+// of width w occupies w consecutive columns, laid out row-major [n][w].  A new block goes
+// right after the previous one (or at column 0 when it would run past the end); the
+// oldest blocks are dropped until it no longer overlaps a stored block, so the arena
+// always holds the most recent blocks (truncation, Section 3, when memory runs out).
+struct QBlock {
+  long long off;  // first column
+  int width;
+};
 struct QStore {
   long long cap = 0;
-  long long count = 0;  // blocks ever stored
-  std::vector<int> width;  // per creation index
+  long long head = 0;
+  std::deque<QBlock> blocks;  // creation order, oldest first
+  long long dropped = 0;      // blocks evicted for lack of room
+  // column offset for the next block of width w; evicts what it overlaps
+  long long place(int w) {
+    long long off = head;
+    if (off + w > cap) off = 0;
+    auto overlaps = [&](const QBlock& b) { return b.off < off + w && off < b.off + b.width; };
+    while (!blocks.empty() && std::any_of(blocks.begin(), blocks.end(), overlaps)) {
+      blocks.pop_front();
+      ++dropped;
+    }
+    return off;
+  }
+  void push(long long off, int w) {
+    blocks.push_back(QBlock{off, w});
+    head = off + w;
+  }
 };
 
 template <typename T>
-int build_spans(const QStore& q, int trunc_eff, T* Qbase, size_t slot_elems, std::vector<Span<T>>& spans) {
+int build_spans(const QStore& q, int trunc, T* Qbase, int n, std::vector<Span<T>>& spans) {
   spans.clear();
-  const long long nact = std::min<long long>(q.count, trunc_eff);
-  const long long first = q.count - nact;
+  const long long total = (long long)q.blocks.size();
+  const long long nact = trunc > 0 ? std::min<long long>(total, trunc) : total;
   int goff = 0;
-  for (long long j = first; j < q.count; ++j) {
-    const long long slot = j % q.cap;
-    const int w = q.width[j];
+  for (long long j = total - nact; j < total; ++j) {
+    const QBlock& b = q.blocks[j];
     if (!spans.empty()) {
       Span<T>& s = spans.back();
-      const long long prev_slot = (j - 1) % q.cap;
-      if (s.width == w && slot == prev_slot + 1) {
+      const QBlock& prev = q.blocks[j - 1];
+      if (s.width == b.width && prev.width == b.width && b.off == prev.off + prev.width) {
         s.nblk += 1;
-        goff += w;
+        goff += b.width;
         continue;
       }
     }
     Span<T> s;
-    s.base = Qbase + (size_t)slot * slot_elems;
-    s.stride = (long long)slot_elems;
+    s.base = Qbase + (size_t)b.off * n;
+    s.stride = (long long)b.width * n;
     s.nblk = 1;
-    s.width = w;
+    s.width = b.width;
     s.goff = goff;
     spans.push_back(s);
-    goff += w;
+    goff += b.width;
   }
   return goff;  // m
 }
@@ -268,6 +296,9 @@ void precond_apply(const ecg_precond* M, int which, int tc, const T* X, T* Y, hi
 }
 
 struct InnerResult {
+  int kmax_left = 0x7fffffff;  // iteration budget left for this solve (all refinement steps)
+  bool stagnated = false;
+  long long dropped = 0;  // stored blocks evicted for lack of room
   int iters = 0;
   int deflated = 0;
   long long mem = 0;
@@ -300,7 +331,6 @@ ecg_status ecg_inner(const ecg_operator* Aop, const ecg_partition* P, const ecg_
   T* Hb = reinterpret_cast<T*>(ws + pl.off_H);
   T* Qbase = reinterpret_cast<T*>(ws + pl.off_Q);
 
-  const long long trunc_eff = (o.trunc > 0) ? std::min<long long>(o.trunc, pl.cap) : pl.cap;
   QStore q;
   q.cap = pl.cap;
   std::vector<Span<T>> spans;
@@ -315,11 +345,14 @@ ecg_status ecg_inner(const ecg_operator* Aop, const ecg_partition* P, const ecg_
 
   double rho_prev = rho0, tol1 = 1.0;
   int k = 1, level = 0;
+  const auto t_begin = std::chrono::steady_clock::now();
   int tl = P->t;                 // live width
   int tc = pow2_at_least(tl);    // padded width of the kernels
   IterStatus hst;
   int prev_kept = tl;
-  while (rho_prev > tol * rho0 && k < o.kmax) {
+  std::vector<double> replaced;  // true residual norms at the residual replacements
+  const int kmax = std::max(1, std::min(o.kmax, res->kmax_left));
+  while (rho_prev > tol * rho0 && k < kmax) {
     // ---- candidate block (cand_live: its columns that are not already known zero)
     bool from_r = false;
     if (k == 1) {
@@ -344,7 +377,7 @@ ecg_status ecg_inner(const ecg_operator* Aop, const ecg_partition* P, const ecg_
       precond_apply<T>(M, 1, tc, Yb, Cb, s);
     }
     // ---- CGS2 against the stored blocks
-    const int m = build_spans<T>(q, (int)trunc_eff, Qbase, pl.slot_elems, spans);
+    const int m = build_spans<T>(q, o.trunc, Qbase, n, spans);
     if (m > 0) {
       for (int pass = 0; pass < 2; ++pass) {
         launch_spmm<T>(A, tc, Cb, Yb, s);
@@ -372,7 +405,8 @@ ecg_status ecg_inner(const ecg_operator* Aop, const ecg_partition* P, const ecg_
     stat_begin(s);
     launch_factor(1, tc, tl, small_out, tau, Cinv, beta, st, s);
     stat_end(kStatFactor, 0.0, (double)tc * tc * tc, s);
-    T* Wslot = Qbase + (size_t)(q.count % q.cap) * pl.slot_elems;
+    const long long woff = q.place(tc);  // may drop the oldest blocks (already used above)
+    T* Wslot = Qbase + (size_t)woff * n;
     const int nwg = launch_final_update<T, TX>(n, tc, Hb, Yb, Cinv, beta, Wslot, Cb, x, r, norm_part, s);
     launch_sum(norm_part, nwg, &st->rr, s);
     HIPCHK(hipMemcpyAsync(&hst, st, sizeof(IterStatus), hipMemcpyDeviceToHost, s));
@@ -390,8 +424,7 @@ ecg_status ecg_inner(const ecg_operator* Aop, const ecg_partition* P, const ecg_
       break;
     }
     // ---- bookkeeping (block stored in its slot by the update kernel)
-    q.width.push_back(tc);
-    q.count += 1;
+    q.push(woff, tc);
     res->mem += hst.keep_a;
     // a column dropped once stays zero in A W, so it is counted only where it is lost
     res->deflated += (from_r ? tl : prev_kept) - hst.keep_a;
@@ -400,6 +433,11 @@ ecg_status ecg_inner(const ecg_operator* Aop, const ecg_partition* P, const ecg_
     tol1 = std::fabs(rho - rho_prev) / rho0;
     rho_prev = rho;
     if (rho_hist) rho_hist[k] = rho;
+    if (g_progress_every > 0 && k % g_progress_every == 0) {
+      std::fprintf(stderr, "ecg: k=%d rho/rho0=%.3e t=%d m=%d elapsed=%.2fs\n", k, rho / rho0, tl, m + tc,
+                   std::chrono::duration<double>(std::chrono::steady_clock::now() - t_begin).count());
+      std::fflush(stderr);
+    }
     if constexpr (std::is_same<T, float>::value) {
       // residual replacement: r = b - A x recomputed in FP64 (x accumulates in FP64)
       if (o.replace_every > 0 && b64_for_replace && k % o.replace_every == 0 &&
@@ -409,11 +447,21 @@ ecg_status ecg_inner(const ecg_operator* Aop, const ecg_partition* P, const ecg_
         HIPCHK(hipMemcpyAsync(&hst, st, sizeof(IterStatus), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         rho_prev = std::sqrt(std::max(hst.rr, 0.0));
+        replaced.push_back(rho_prev);
+        // stagnation: the true residual fell by less than 10% over the last four
+        // replacements; hand back to the FP64 refinement step
+        const size_t nr = replaced.size();
+        if (nr > 4 && replaced[nr - 1] > 0.9 * replaced[nr - 5]) {
+          ++k;
+          res->stagnated = true;
+          break;
+        }
       }
     }
     ++k;
   }
   res->iters = k - 1;
+  res->dropped += q.dropped;
   res->rho = rho_prev;
   res->t_final = tl;
   if (res->status == ECG_OK && rho_prev > tol * rho0) res->status = ECG_ENOTCONV;
@@ -599,6 +647,11 @@ void ecg::stat_end(int cls, double bytes, double flops, hipStream_t s) {
 
 // ====================================================================== C ABI
 extern "C" {
+
+ecg_status ecg_progress(int32_t every) {
+  g_progress_every = every > 0 ? every : 0;
+  return ECG_OK;
+}
 
 ecg_status ecg_stats_enable(int on) {
   g_stats_on = on != 0;
@@ -905,14 +958,18 @@ ecg_status ecg_solve(const ecg_operator* A, const ecg_partition* P, const double
       HIPCHK(hipMemsetAsync(d, 0, (size_t)n * 8, s));
       launch_cast_d2f(n, r64, rf, s);
       InnerResult ir;
+      ir.kmax_left = o->kmax - tot.iters;
+      if (ir.kmax_left < 2) break;
       // the inner tolerance is relative to the inner initial residual, but never asks for
       // more than the outer target
       const double itol = std::max(o->inner_tol, o->tol * rho0 / std::sqrt(rr) * 0.5);
+      const double rr_before = rr;
       st = ecg_inner<float, double>(A, P, *o, pl, ws, d, rf, rr, itol, r64, s, &ir, nullptr);
       if (st != ECG_OK) return st;
       tot.iters += ir.iters;
       tot.mem += ir.mem;
       tot.deflated += ir.deflated;
+      tot.dropped += ir.dropped;
       for (int sw : ir.switches) tot.switches.push_back(sw);
       tot.t_final = ir.t_final;
       ++outer;
@@ -926,6 +983,7 @@ ecg_status ecg_solve(const ecg_operator* A, const ecg_partition* P, const double
       HIPCHK(hipMemcpyAsync(&rr, dscal, 8, hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
       tot.rho = std::sqrt(rr);
+      if (!(rr < 0.81 * rr_before)) break;  // a refinement step that gains < 10%: give up
     }
     if (final != ECG_EBREAKDOWN && std::sqrt(rr) <= o->tol * rho0) final = ECG_OK;
     rep->relres_recursive = rho0 > 0 ? std::sqrt(rr) / rho0 : 0.0;
@@ -945,7 +1003,8 @@ ecg_status ecg_solve(const ecg_operator* A, const ecg_partition* P, const double
   rep->t_final = tot.t_final;
   rep->outer_iters = outer;
   rep->deflated_cols = tot.deflated;
-  rep->trunc_used = (o->trunc > 0 || pl.cap < o->kmax - 1) ? (int)std::min<long long>(pl.cap, o->trunc > 0 ? o->trunc : pl.cap) : 0;
+  rep->trunc_used = o->trunc > 0 ? o->trunc : 0;
+  rep->blocks_dropped = (int32_t)std::min<long long>(tot.dropped, 0x7fffffff);
   rep->vectors_stored = tot.mem;
   rep->seconds = std::chrono::duration<double>(t_end - t_start).count();
   rep->status = final;
@@ -984,7 +1043,7 @@ ecg_status ecg_debug_gram(int64_t n, int32_t nb, int32_t wq, const double* Q, in
   hipStream_t s = (hipStream_t)hip_stream;
   Span<double> sp{Q, (long long)n * wq, nb, wq, 0};
   const int m = nb * wq;
-  const size_t cap = (size_t)2048 * 64 * 64;
+  const size_t cap = (size_t)1 << 26;
   double* part = nullptr;
   HIPCHK(hipMalloc(&part, cap * sizeof(double)));
   launch_gram<double>((int)n, &sp, 1, m, t, Y, G, part, cap, s);

@@ -11,7 +11,7 @@ namespace ecg {
 
 constexpr int kBlock = 256;      // threads per workgroup for streaming kernels
 constexpr int kMaxT = 64;        // widest block (t x t factor runs in one workgroup)
-constexpr int kSmallChunks = 512;  // partial sums of the t x t Grams and norms
+constexpr int kSmallChunks = 1024;  // partial sums of the t x t Grams
 
 // Device copy of a sparse matrix in CSR form (int32 row pointers).
 struct DevCsr {

@@ -96,6 +96,18 @@ __global__ void __launch_bounds__(kBlock) k_sum(const double* __restrict__ part,
   if (threadIdx.x == 0) *out = tot;
 }
 
+// First stage of a long sum: workgroup b adds the fixed slice [b*per, (b+1)*per).
+__global__ void __launch_bounds__(kBlock)
+k_sum_stage(const double* __restrict__ part, int m, int per, double* __restrict__ out) {
+  __shared__ double red[kBlock];
+  const int lo = blockIdx.x * per;
+  const int hi = min(m, lo + per);
+  double acc = 0.0;
+  for (int i = lo + threadIdx.x; i < hi; i += kBlock) acc += part[i];
+  const double tot = block_sum(acc, red);
+  if (threadIdx.x == 0) out[blockIdx.x] = tot;
+}
+
 __global__ void __launch_bounds__(kBlock) k_cast_d2f(int n, const double* __restrict__ in, float* __restrict__ out) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i < n) out[i] = (float)in[i];
@@ -226,6 +238,227 @@ k_update(int n, int nwg, Span<T> sp, const T* __restrict__ G, T* __restrict__ W)
   if (row < n) W[(size_t)row * TC + b] -= acc;
 }
 
+// ------------------------------------------------------------------ MFMA tall-skinny products
+// 16x16x4 matrix-core tiles (FP64: v_mfma_f64_16x16x4f64, FP32: v_mfma_f32_16x16x4f32).
+// Operand layout of one wavefront: lane l supplies A[l%16][l/16] and B[l/16][l%16];
+// the 16x16 result sits in 4 values per lane v = 0..3 at column l%16 and row
+// 4*(l/16)+v for FP32 but (l/16)+4*v for FP64 (checked on gfx950 with a lane probe).
+typedef double mf_d4 __attribute__((ext_vector_type(4)));
+typedef float mf_f4 __attribute__((ext_vector_type(4)));
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  using V = mf_d4;
+  __device__ __forceinline__ static V run(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ __forceinline__ static int row(int g, int v) { return g + 4 * v; }
+};
+template <>
+struct Mfma<float> {
+  using V = mf_f4;
+  __device__ __forceinline__ static V run(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ __forceinline__ static int row(int g, int v) { return 4 * g + v; }
+};
+
+// Q columns handled by one Gram wavefront (more columns = fewer re-reads of Y).
+template <typename T, int WQ, int TC>
+struct GramTile {
+  static constexpr int QC = (TC >= 64 || sizeof(T) == 8) ? 64 : 128;
+  static constexpr int JB = QC >= WQ ? QC / WQ : 1;
+};
+
+// CGS2 Gram on matrix cores: one wavefront = JB stored blocks x one chunk of rows.
+// K of the 16x16x4 product runs over rows (4 rows per instruction, lane group g = l/16
+// takes row r+g).  M and N are interleaved so that each lane reads TA (TB) consecutive
+// values of a row with one vector load: tile ta pairs M-index i with Q column TA*i+ta,
+// tile tb pairs N-index j with Y column TB*j+tb.  Sixteen rows are loaded before the
+// products of the first four start, to keep enough loads in flight.
+template <typename T, int WQ, int TC>
+__global__ void __launch_bounds__(64)
+k_gram_mfma(int n, Span<T> sp, int rows_per_chunk, int units, int nwork, const T* __restrict__ Y,
+            T* __restrict__ part, int m) {
+  using V = typename Mfma<T>::V;
+  constexpr int JB = GramTile<T, WQ, TC>::JB;
+  constexpr int TA = WQ / 16, TB = TC / 16;
+  typedef T TAv __attribute__((ext_vector_type(TA)));
+  typedef T TBv __attribute__((ext_vector_type(TB)));
+  constexpr int RQ = 4;  // row quads loaded ahead
+  const int lane = threadIdx.x;
+  const int g = lane >> 4, c = lane & 15;
+  // chunk-major order, one contiguous range per XCD: the workgroups that share a chunk
+  // of Y run together on one XCD and read it from that XCD's L2
+  const int w = xcd_block();
+  if (w >= nwork) return;
+  const int chunk = w / units;
+  const int j0 = (w % units) * JB;
+  const int r0 = chunk * rows_per_chunk;
+  const int r1 = min(n, r0 + rows_per_chunk);
+  V acc[JB][TA][TB];
+#pragma unroll
+  for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+    for (int ta = 0; ta < TA; ++ta)
+#pragma unroll
+      for (int tb = 0; tb < TB; ++tb) acc[jb][ta][tb] = V{0, 0, 0, 0};
+  const T* __restrict__ Qb[JB];
+  bool jv[JB];
+#pragma unroll
+  for (int jb = 0; jb < JB; ++jb) {
+    jv[jb] = (j0 + jb) < sp.nblk;
+    Qb[jb] = sp.base + (size_t)(jv[jb] ? j0 + jb : j0) * sp.stride + TA * c;
+  }
+  const T* __restrict__ Yc = Y + TB * c;
+  // operands of 4*RQ rows, double-buffered: the next batch is requested before the
+  // products of the current one are issued
+  TAv qa0[RQ][JB], qa1[RQ][JB];
+  TBv yb0[RQ], yb1[RQ];
+  auto load = [&](TAv (&qa)[RQ][JB], TBv (&yb)[RQ], int row) {
+#pragma unroll
+    for (int q = 0; q < RQ; ++q) {
+      const int rr = row + 4 * q + g;
+      const bool ok = rr < r1;
+      yb[q] = ok ? *reinterpret_cast<const TBv*>(Yc + (size_t)rr * TC) : TBv(0);
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb)  // Q is streamed once: keep it out of the caches
+        qa[q][jb] = (ok && jv[jb]) ? __builtin_nontemporal_load(reinterpret_cast<const TAv*>(Qb[jb] + (size_t)rr * WQ))
+                                   : TAv(0);
+    }
+  };
+  auto product = [&](const TAv (&qa)[RQ][JB], const TBv (&yb)[RQ]) {
+#pragma unroll
+    for (int q = 0; q < RQ; ++q)
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+        for (int ta = 0; ta < TA; ++ta)
+#pragma unroll
+          for (int tb = 0; tb < TB; ++tb)
+            acc[jb][ta][tb] = Mfma<T>::run(qa[q][jb][ta], yb[q][tb], acc[jb][ta][tb]);
+  };
+  load(qa0, yb0, r0);
+  int row = r0;
+  for (; row + 4 * RQ < r1; row += 8 * RQ) {
+    load(qa1, yb1, row + 4 * RQ);
+    product(qa0, yb0);
+    load(qa0, yb0, row + 8 * RQ);  // past the chunk: zeros, no memory access
+    product(qa1, yb1);
+  }
+  if (row < r1) product(qa0, yb0);
+#pragma unroll
+  for (int jb = 0; jb < JB; ++jb) {
+    if (!jv[jb]) continue;
+    const size_t rowbase = (size_t)chunk * m + sp.goff + (size_t)(j0 + jb) * WQ;
+#pragma unroll
+    for (int ta = 0; ta < TA; ++ta)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const size_t a = rowbase + TA * Mfma<T>::row(g, v) + ta;
+#pragma unroll
+        for (int tb = 0; tb < TB; ++tb) part[a * TC + TB * c + tb] = acc[jb][ta][tb][v];
+      }
+  }
+}
+
+// CGS2 update W -= Q G on matrix cores.  A workgroup owns 256 rows (4 wavefronts x 4 row
+// tiles of 16); K runs over stored columns.  Each lane reads 4 consecutive columns of one
+// row of Q (a 16/32-byte vector load), so instruction s of a 16-column chunk pairs lane
+// group g with column 4g+s; the matching rows of G come from LDS.  G is staged KS
+// columns at a time in two LDS buffers: the next stage is fetched into registers while
+// the current one is multiplied, so each stage costs one barrier.
+template <typename T, int WQ, int TC>
+struct UpdateTile {
+  static constexpr int KS = (WQ > 64 ? WQ : 64);        // stored columns per stage
+  static constexpr int JS = KS / WQ;                    // blocks per stage
+  static constexpr int NE = KS * TC;                    // G values per stage
+  static constexpr int PER = (NE + kBlock - 1) / kBlock;  // per thread
+};
+
+template <typename T, int WQ, int TC>
+__global__ void __launch_bounds__(kBlock)
+k_update_mfma(int n, int nwg, Span<T> sp, const T* __restrict__ G, T* __restrict__ W) {
+  using V = typename Mfma<T>::V;
+  typedef T T4 __attribute__((ext_vector_type(4)));
+  using U = UpdateTile<T, WQ, TC>;
+  constexpr int TB = TC / 16, RT = 4;
+  __shared__ T Gs[2][U::NE];
+  const int blk = xcd_block();
+  if (blk >= nwg) return;  // the whole workgroup leaves together
+  const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+  const int g = lane >> 4, c = lane & 15;
+  const int rowbase = blk * 256 + wave * 64;
+  const int nst = (sp.nblk + U::JS - 1) / U::JS;
+  const T* __restrict__ Gspan = G + (size_t)sp.goff * TC;
+  const int total = sp.nblk * WQ * TC;  // G values of this span
+  V acc[RT][TB];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int tb = 0; tb < TB; ++tb) acc[rt][tb] = V{0, 0, 0, 0};
+  T pre[U::PER];
+  auto fetch = [&](int st) {
+#pragma unroll
+    for (int i = 0; i < U::PER; ++i) {
+      const int e = (int)threadIdx.x + i * kBlock;
+      const int ge = st * U::NE + e;
+      pre[i] = (e < U::NE && ge < total) ? Gspan[ge] : T(0);
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < U::PER; ++i) {
+      const int e = (int)threadIdx.x + i * kBlock;
+      if (e < U::NE) Gs[buf][e] = pre[i];
+    }
+  };
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int cur = st & 1;
+    if (st + 1 < nst) fetch(st + 1);
+    const int jn = min(U::JS, sp.nblk - st * U::JS);
+    for (int jb = 0; jb < jn; ++jb) {
+      const T* __restrict__ Qj = sp.base + (size_t)(st * U::JS + jb) * sp.stride;
+#pragma unroll
+      for (int kc = 0; kc < WQ / 16; ++kc) {
+        T4 q[RT];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+          const int row = rowbase + rt * 16 + c;
+          q[rt] = row < n ? *reinterpret_cast<const T4*>(Qj + (size_t)row * WQ + kc * 16 + 4 * g) : T4{0, 0, 0, 0};
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int kk = jb * WQ + kc * 16 + 4 * g + s;
+          T gv[TB];
+#pragma unroll
+          for (int tb = 0; tb < TB; ++tb) gv[tb] = Gs[cur][kk * TC + tb * 16 + c];
+#pragma unroll
+          for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int tb = 0; tb < TB; ++tb) acc[rt][tb] = Mfma<T>::run(q[rt][s], gv[tb], acc[rt][tb]);
+        }
+      }
+    }
+    if (st + 1 < nst) stash(cur ^ 1);  // that buffer was last read before the previous barrier
+    __syncthreads();
+  }
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = rowbase + rt * 16 + Mfma<T>::row(g, v);
+      if (row < n) {
+#pragma unroll
+        for (int tb = 0; tb < TB; ++tb) W[(size_t)row * TC + tb * 16 + c] -= acc[rt][tb][v];
+      }
+    }
+}
+
 // ------------------------------------------------------------------ t x t Grams (FP64)
 template <typename T, int TC, bool WITH_R>
 __global__ void __launch_bounds__(kBlock)
@@ -259,6 +492,63 @@ k_small_gram(int n, int rows_per_chunk, const T* __restrict__ X, const T* __rest
   }
 }
 
+// t x t Grams on FP64 matrix cores (FP32 data is widened on load, so these Grams are
+// accumulated in FP64 in both precisions).  One wavefront per chunk of rows; K runs over
+// rows.  Tile ta pairs M-index i with column TA*i+ta of X, tile tb < TB pairs N-index j with
+// column TB*j+tb of Y; with WITH_R one more tile carries r in its column 0 (u = X^T r).
+template <typename T, int TC, bool WITH_R>
+__global__ void __launch_bounds__(64)
+k_small_gram_mfma(int n, int rows_per_chunk, const T* __restrict__ X, const T* __restrict__ Y,
+                  const T* __restrict__ r, double* __restrict__ part) {
+  using V = Mfma<double>::V;
+  constexpr int TA = TC / 16, TB = TC / 16, TR = TB + (WITH_R ? 1 : 0);
+  constexpr int NOUT = TC * TC + (WITH_R ? TC : 0);
+  typedef T Tv __attribute__((ext_vector_type(TA)));
+  const int lane = threadIdx.x;
+  const int g = lane >> 4, c = lane & 15;
+  const int chunk = blockIdx.x;
+  const int r0 = chunk * rows_per_chunk;
+  const int r1 = min(n, r0 + rows_per_chunk);
+  V acc[TA][TR];
+#pragma unroll
+  for (int ta = 0; ta < TA; ++ta)
+#pragma unroll
+    for (int tb = 0; tb < TR; ++tb) acc[ta][tb] = V{0, 0, 0, 0};
+  for (int row = r0; row < r1; row += 16) {
+    Tv xa[4], yb[4];
+    double rv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int rr = row + 4 * q + g;
+      const bool ok = rr < r1;
+      xa[q] = ok ? *reinterpret_cast<const Tv*>(X + (size_t)rr * TC + TA * c) : Tv(0);
+      yb[q] = ok ? *reinterpret_cast<const Tv*>(Y + (size_t)rr * TC + TB * c) : Tv(0);
+      rv[q] = (WITH_R && ok && c == 0) ? (double)r[rr] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int ta = 0; ta < TA; ++ta) {
+#pragma unroll
+        for (int tb = 0; tb < TB; ++tb)
+          acc[ta][tb] = Mfma<double>::run((double)xa[q][ta], (double)yb[q][tb], acc[ta][tb]);
+        if constexpr (WITH_R) acc[ta][TB] = Mfma<double>::run((double)xa[q][ta], rv[q], acc[ta][TB]);
+      }
+  }
+  double* __restrict__ out = part + (size_t)chunk * NOUT;
+#pragma unroll
+  for (int ta = 0; ta < TA; ++ta)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int a = TA * Mfma<double>::row(g, v) + ta;
+#pragma unroll
+      for (int tb = 0; tb < TB; ++tb) out[a * TC + TB * c + tb] = acc[ta][tb][v];
+      if constexpr (WITH_R) {
+        if (c == 0) out[TC * TC + a] = acc[ta][TB][v];
+      }
+    }
+}
+
 __global__ void __launch_bounds__(kBlock)
 k_reduce_small(int len, int nchunks, const double* __restrict__ part, double* __restrict__ out) {
   const int e = blockIdx.x * kBlock + threadIdx.x;
@@ -266,6 +556,18 @@ k_reduce_small(int len, int nchunks, const double* __restrict__ part, double* __
   double s = 0.0;
   for (int c = 0; c < nchunks; ++c) s += part[(size_t)c * len + e];
   out[e] = s;
+}
+
+// First stage: split y of the chunks [y*per, (y+1)*per) summed in order into mid[y][e].
+__global__ void __launch_bounds__(kBlock)
+k_reduce_small_stage(int len, int nchunks, int per, const double* __restrict__ part, double* __restrict__ mid) {
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e >= len) return;
+  const int c0 = blockIdx.y * per;
+  const int c1 = min(nchunks, c0 + per);
+  double s = 0.0;
+  for (int c = c0; c < c1; ++c) s += part[(size_t)c * len + e];
+  mid[(size_t)blockIdx.y * len + e] = s;
 }
 
 // ------------------------------------------------------------------ t x t factor (FP64)
@@ -553,7 +855,16 @@ void launch_spmv(const DevCsr& A, const double* x, double* y, hipStream_t s) {
 }
 
 void launch_sum(const double* part, int m, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_sum, dim3(1), dim3(kBlock), 0, s, part, m, out);
+  if (m <= 8192) {
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(kBlock), 0, s, part, m, out);
+    return;
+  }
+  // two stages: 128 slices, then their sum; the slices live past the end of `part`
+  const int nb = 128;
+  const int per = cdiv(m, nb);
+  double* mid = const_cast<double*>(part) + m;
+  hipLaunchKernelGGL(k_sum_stage, dim3(nb), dim3(kBlock), 0, s, part, m, per, mid);
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(kBlock), 0, s, mid, nb, out);
 }
 
 void launch_cast_d2f(int n, const double* in, float* out, hipStream_t s) {
@@ -629,21 +940,43 @@ void launch_split_t(int n, const int* part, int level, int tc, const T* v, T* ou
   }
 }
 
-// Chunk count for the CGS2 Gram: enough workgroups to fill 256 CUs several times over,
-// but at least 256 rows per chunk.
-static int gram_chunks(int n, int nblk_total, size_t part_cap, int m, int tc) {
-  int nch = 2048 / (nblk_total > 0 ? nblk_total : 1);
-  nch = nch < 1 ? 1 : nch;
+// Work units of one span: Gram wavefronts/workgroups along the block axis.
+template <typename T>
+static int gram_units(const Span<T>& sp, int tc) {
+  if (sp.width >= 16 && tc >= 16) {
+    const int jb = ((tc >= 64 || sizeof(T) == 8) ? 64 : 128) / sp.width;
+    const int JB = jb < 1 ? 1 : jb;
+    return (sp.nblk + JB - 1) / JB;
+  }
+  return sp.nblk;
+}
+
+// Row chunks of the CGS2 Gram: a chunk of Y is at most 1 MiB (it is re-read by every
+// block group, from L2), there are enough work units to fill 256 CUs many times over, at
+// least 256 rows per chunk, and the partial sums fit the workspace.
+static int gram_chunks(int n, int units, size_t part_cap, int m, int tc, int elt) {
+  units = units > 0 ? units : 1;
+  int nch = cdiv((long long)n * tc * elt, 1 << 20);
+  const int want = cdiv(4096, units);
+  if (nch < want) nch = want;
   const int maxc = cdiv(n, 256);
   if (nch > maxc) nch = maxc;
-  while (nch > 1 && (size_t)nch * m * tc > part_cap) --nch;
-  return nch;
+  while (nch > 1 && (size_t)nch * m * tc > part_cap) nch = (nch + 1) / 2 < nch ? (nch + 1) / 2 : nch - 1;
+  return nch < 1 ? 1 : nch;
 }
 
 template <typename T, int WQ, int TC>
 static void gram_span(int n, const Span<T>& sp, int rpc, int nch, const T* Y, T* part, int m, hipStream_t s) {
   stat_begin(s);
-  hipLaunchKernelGGL((k_gram<T, WQ, TC>), dim3(sp.nblk, nch), dim3(kBlock), 0, s, n, sp, rpc, Y, part, m);
+  if constexpr (WQ >= 16 && TC >= 16) {
+    constexpr int JB = GramTile<T, WQ, TC>::JB;
+    const int units = (sp.nblk + JB - 1) / JB;
+    const int nwork = units * nch;
+    hipLaunchKernelGGL((k_gram_mfma<T, WQ, TC>), dim3(pad8(nwork)), dim3(64), 0, s, n, sp, rpc, units, nwork, Y,
+                       part, m);
+  } else {
+    hipLaunchKernelGGL((k_gram<T, WQ, TC>), dim3(sp.nblk, nch), dim3(kBlock), 0, s, n, sp, rpc, Y, part, m);
+  }
   stat_end(kStatGram, (double)sizeof(T) * n * ((double)sp.nblk * WQ + TC), 2.0 * n * sp.nblk * WQ * TC, s);
 }
 
@@ -662,10 +995,11 @@ static void gram_span_wq(int n, const Span<T>& sp, int rpc, int nch, const T* Y,
 template <typename T>
 void launch_gram(int n, const Span<T>* spans, int nspan, int m, int tc, const T* Y, T* G, T* part_buf,
                  size_t part_cap, hipStream_t s) {
-  int nblk = 0;
-  for (int i = 0; i < nspan; ++i) nblk += spans[i].nblk;
-  const int nch = gram_chunks(n, nblk, part_cap, m, tc);
-  const int rpc = cdiv(n, nch);
+  int units = 0;
+  for (int i = 0; i < nspan; ++i) units += gram_units(spans[i], tc);
+  int nch = gram_chunks(n, units, part_cap, m, tc, (int)sizeof(T));
+  const int rpc = (cdiv(n, nch) + 15) / 16 * 16;  // multiple of 16 rows (one load batch)
+  nch = cdiv(n, rpc);
   T* dst = (nch == 1) ? G : part_buf;
   for (int i = 0; i < nspan; ++i) {
     switch (tc) {
@@ -687,15 +1021,21 @@ void launch_gram(int n, const Span<T>* spans, int nspan, int m, int tc, const T*
 
 template <typename T, int TC>
 static void update_span(int n, const Span<T>& sp, const T* G, T* W, hipStream_t s) {
-  const int nwg = cdiv(n, kBlock / TC);
   switch (sp.width) {
-#define C(WQ)                                                                                     \
-  case WQ:                                                                                        \
-    stat_begin(s);                                                                               \
-    hipLaunchKernelGGL((k_update<T, WQ, TC>), dim3(pad8(nwg)), dim3(kBlock), 0, s, n, nwg, sp, G, W); \
-    stat_end(kStatUpdate, (double)sizeof(T) * n * ((double)sp.nblk * WQ + 2.0 * TC),             \
-             2.0 * n * sp.nblk * WQ * TC, s);                                                    \
-    break;
+#define C(WQ)                                                                                          \
+  case WQ: {                                                                                           \
+    stat_begin(s);                                                                                     \
+    if constexpr (WQ >= 16 && TC >= 16) {                                                              \
+      const int nwg = cdiv(n, 256);                                                                    \
+      hipLaunchKernelGGL((k_update_mfma<T, WQ, TC>), dim3(pad8(nwg)), dim3(kBlock), 0, s, n, nwg, sp, G, W); \
+    } else {                                                                                           \
+      const int nwg = cdiv(n, kBlock / TC);                                                            \
+      hipLaunchKernelGGL((k_update<T, WQ, TC>), dim3(pad8(nwg)), dim3(kBlock), 0, s, n, nwg, sp, G, W); \
+    }                                                                                                  \
+    stat_end(kStatUpdate, (double)sizeof(T) * n * ((double)sp.nblk * WQ + 2.0 * TC),                   \
+             2.0 * n * sp.nblk * WQ * TC, s);                                                          \
+    break;                                                                                             \
+  }
     ECG_TC_CASES(C)
 #undef C
   }
@@ -720,8 +1060,31 @@ void launch_small_gram(int n, int tc, const T* X, const T* Y, const T* r, double
                        hipStream_t s) {
   int nch = cdiv(n, 256);
   if (nch > kSmallChunks) nch = kSmallChunks;
-  const int rpc = cdiv(n, nch);
   const int nout = tc * tc + (r ? tc : 0);
+  if (tc >= 16) {
+    const int rpc = (cdiv(n, nch) + 15) / 16 * 16;
+    nch = cdiv(n, rpc);
+    switch (tc) {
+#define C(TC)                                                                                                   \
+  case TC:                                                                                                      \
+    if (r)                                                                                                      \
+      hipLaunchKernelGGL((k_small_gram_mfma<T, TC, true>), dim3(nch), dim3(64), 0, s, n, rpc, X, Y, r, part);   \
+    else                                                                                                        \
+      hipLaunchKernelGGL((k_small_gram_mfma<T, TC, false>), dim3(nch), dim3(64), 0, s, n, rpc, X, Y, r, part);  \
+    break;
+      C(16) C(32) C(64)
+#undef C
+    }
+    // two-stage chunk sum; the 32 intermediate rows live past the chunk partials
+    const int nsplit = 32;
+    const int per = cdiv(nch, nsplit);
+    double* mid = part + (size_t)nch * nout;
+    hipLaunchKernelGGL(k_reduce_small_stage, dim3(cdiv(nout, kBlock), nsplit), dim3(kBlock), 0, s, nout, nch, per,
+                       part, mid);
+    hipLaunchKernelGGL(k_reduce_small, dim3(cdiv(nout, kBlock)), dim3(kBlock), 0, s, nout, nsplit, mid, out);
+    return;
+  }
+  const int rpc = cdiv(n, nch);
   switch (tc) {
 #define C(TC)                                                                                        \
   case TC:                                                                                           \

@@ -33,7 +33,7 @@ EXPORTED = (
     "ecg_partition_create", "ecg_partition_destroy", "ecg_precond_create_bj_ic0",
     "ecg_precond_create_factor", "ecg_precond_destroy", "ecg_workspace_size", "ecg_solve", "ecg_spmv",
     "ecg_last_error", "ecg_debug_spmm", "ecg_debug_split", "ecg_debug_gram", "ecg_debug_update",
-    "ecg_debug_precond_apply", "ecg_stats_enable", "ecg_stats_read",
+    "ecg_debug_precond_apply", "ecg_stats_enable", "ecg_stats_read", "ecg_progress",
 )
 STAT_NAMES = ("spmm", "cgs2_gram", "cgs2_gram_reduce", "cgs2_update", "small_gram", "factor",
               "times_small", "final_update", "split_precond", "vector")
@@ -70,6 +70,7 @@ class Report(C.Structure):
         ("outer_iters", C.c_int32),
         ("deflated_cols", C.c_int32),
         ("trunc_used", C.c_int32),
+        ("blocks_dropped", C.c_int32),
         ("vectors_stored", C.c_int64),
         ("relres_recursive", C.c_double),
         ("relres_true", C.c_double),
@@ -85,6 +86,7 @@ class Report(C.Structure):
             "outer_iters": self.outer_iters,
             "deflated_cols": self.deflated_cols,
             "trunc_used": self.trunc_used,
+            "blocks_dropped": self.blocks_dropped,
             "vectors_stored": int(self.vectors_stored),
             "relres_recursive": self.relres_recursive,
             "relres_true": self.relres_true,
@@ -133,6 +135,7 @@ def lib():
             "ecg_debug_update": (i32, [i64, i32, i32, dp, i32, dp, dp, vp]),
             "ecg_debug_precond_apply": (i32, [vp, i32, i32, dp, dp, vp]),
             "ecg_stats_enable": (i32, [C.c_int]),
+            "ecg_progress": (i32, [i32]),
             "ecg_stats_read": (i32, [C.POINTER(KernelStats), C.c_int]),
         }
         for name, (res, args) in sig.items():
@@ -331,3 +334,8 @@ def stats_read(reset: bool = True) -> dict:
     check(lib().ecg_stats_read(C.byref(st), 1 if reset else 0))
     return {name: {"count": int(st.count[i]), "ms": st.ms[i], "bytes": st.bytes[i], "flops": st.flops[i]}
             for i, name in enumerate(STAT_NAMES)}
+
+
+def progress(every: int):
+    """Print a progress line to stderr every `every` iterations (0 = off)."""
+    check(lib().ecg_progress(int(every)))
