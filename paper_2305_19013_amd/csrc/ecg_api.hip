@@ -631,6 +631,8 @@ ecg_status make_tri(int64_t n, const std::vector<int>& group, int ngroups, const
 
 }  // namespace
 
+void ecg::set_last_error(const char* msg) { g_err = msg ? msg : ""; }
+
 void ecg::stat_begin(hipStream_t s) {
   if (!g_stats_on) return;
   g_open = take_event();

@@ -50,6 +50,9 @@ enum StatClass {
   kStatFactor = 5, kStatTimesSmall = 6, kStatFinal = 7, kStatSplit = 8, kStatVector = 9, kNumStat = 10
 };
 extern bool g_stats_on;
+// Message returned by ecg_last_error() (thread-local), for translation units other than
+// the driver.
+void set_last_error(const char* msg);
 // Record an event before a launch / after it (no-ops unless timing is enabled).
 void stat_begin(hipStream_t s);
 void stat_end(int cls, double bytes, double flops, hipStream_t s);

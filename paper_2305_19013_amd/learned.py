@@ -1,0 +1,261 @@
+"""Learned preconditioner M^{-1} = G G^T: binding of include/ecg_nn.h and its training loop.
+
+Everything numerical runs in libecg.so: the network forward/backward, the loss and its
+gradient, Adam, the CSR of G, and the ECG solves that produce the training solutions.
+This module only moves arguments, picks minibatches and loops.
+
+Usage (trains on operators of the learn2d256 family and evaluates on held-out seeds):
+    python -m paper_2305_19013_amd.learned --train 256 --heldout 16 --epochs 4
+"""
+
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import ecg as E
+
+NPARAM = 1411
+_sig_done = False
+
+
+def _lib():
+    global _sig_done
+    L = E.lib()
+    if not _sig_done:
+        vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+        sig = {
+            "ecg_nn_forward": [i32, i32, i32, vp, vp, vp, vp],
+            "ecg_nn_workspace_size": [i32, i32, i32, C.POINTER(C.c_size_t)],
+            "ecg_nn_loss_grad": [i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp],
+            "ecg_nn_backward": [i32, i32, i32, vp, vp, vp, C.c_double, vp, vp, C.c_size_t, vp],
+            "ecg_nn_adam": [i32, vp, vp, vp, vp, i32, C.c_double, C.c_double, C.c_double, C.c_double, vp],
+            "ecg_nn_factor_csr": [i32, i32, vp, vp, vp, vp, vp],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.restype = C.c_int32
+            fn.argtypes = args
+        _sig_done = True
+    return L
+
+
+def _p(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class LearnedFactor:
+    """Network parameters (FP32) and Adam state (FP64) on the device, for an nx x ny grid."""
+
+    def __init__(self, nx: int, ny: int, params0, device):
+        import torch
+
+        self.torch = torch
+        self.nx, self.ny, self.n = int(nx), int(ny), int(nx) * int(ny)
+        self.device = device
+        self.params = torch.tensor(np.asarray(params0), dtype=torch.float32, device=device)
+        self.m = torch.zeros(NPARAM, dtype=torch.float64, device=device)
+        self.v = torch.zeros(NPARAM, dtype=torch.float64, device=device)
+        self.grad = torch.zeros(NPARAM, dtype=torch.float64, device=device)
+        self.step = 0
+        self._ws = {}
+
+    def _workspace(self, nb):
+        if nb not in self._ws:
+            sz = C.c_size_t()
+            E.check(_lib().ecg_nn_workspace_size(self.nx, self.ny, nb, C.byref(sz)))
+            self._ws[nb] = self.torch.empty(sz.value, dtype=self.torch.uint8, device=self.device)
+        return self._ws[nb]
+
+    def forward(self, a5):
+        nb = a5.shape[0]
+        g3 = self.torch.empty((nb, 3, self.n), dtype=self.torch.float64, device=self.device)
+        E.check(_lib().ecg_nn_forward(self.nx, self.ny, nb, _p(a5), _p(self.params), _p(g3), E._stream()))
+        return g3
+
+    def loss_grad(self, a5, g3, b, x):
+        nb = a5.shape[0]
+        ws = self._workspace(nb)
+        loss = self.torch.empty(nb, dtype=self.torch.float64, device=self.device)
+        dg3 = self.torch.empty_like(g3)
+        E.check(_lib().ecg_nn_loss_grad(self.nx, self.ny, nb, _p(a5), _p(g3), _p(b), _p(x), _p(loss), _p(dg3),
+                                        _p(ws), ws.numel(), E._stream()))
+        return loss, dg3
+
+    def backward(self, a5, dg3, scale):
+        nb = a5.shape[0]
+        ws = self._workspace(nb)
+        E.check(_lib().ecg_nn_backward(self.nx, self.ny, nb, _p(a5), _p(self.params), _p(dg3), float(scale),
+                                       _p(self.grad), _p(ws), ws.numel(), E._stream()))
+        return self.grad
+
+    def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.step += 1
+        E.check(_lib().ecg_nn_adam(NPARAM, _p(self.params), _p(self.grad), _p(self.m), _p(self.v), self.step,
+                                   lr, beta1, beta2, eps, E._stream()))
+
+    def train_step(self, a5, b, x, lr):
+        """One minibatch: forward, loss and dL/dG, backward (batch mean), Adam."""
+        g3 = self.forward(a5)
+        loss, dg3 = self.loss_grad(a5, g3, b, x)
+        self.backward(a5, dg3, 1.0 / a5.shape[0])
+        self.adam(lr)
+        return loss
+
+    def preconditioner(self, a5_one):
+        """E.Precond for one operator (a5_one: [1, 5, n]) built from the network's G."""
+        torch = self.torch
+        g3 = self.forward(a5_one)
+        nnz = 3 * self.n - self.nx - self.ny
+        rowptr = torch.empty(self.n + 1, dtype=torch.int64, device=self.device)
+        col = torch.empty(nnz, dtype=torch.int32, device=self.device)
+        val = torch.empty(nnz, dtype=torch.float64, device=self.device)
+        E.check(_lib().ecg_nn_factor_csr(self.nx, self.ny, _p(g3), _p(rowptr), _p(col), _p(val), E._stream()))
+        return E.Precond.factor_device(self.n, nnz, rowptr, col, val)
+
+
+# ----------------------------------------------------------------------------- data
+def family(seed: int, scale: int = 1):
+    """Operator `seed` of the learn2d256 family (problem, 5-point stencil)."""
+    import workloads as W
+
+    p = W.config("learn2d256", seed=seed, scale=scale)
+    return p, W.stencil5(p.A, p.grid[0])
+
+
+def solve_dataset(seeds, device, scale=1, tol=1e-10, log=print):
+    """Solutions x_s = A_s^{-1} b_s produced by the ECG solver itself (FP64, block-Jacobi
+    IC(0) on the t = 16 subdomains).  Returns device tensors a5 [N,5,n], b [N,n], x [N,n]."""
+    import torch
+
+    A5, B, X = [], [], []
+    t0 = time.time()
+    for j, s in enumerate(seeds):
+        p, a5 = family(s, scale)
+        op = E.Operator.from_csr(p.A)
+        P = E.Partition(p.part, p.t)
+        M = E.Precond.bj_ic0(op, P)
+        b = torch.from_numpy(p.b).to(device)
+        x = torch.zeros_like(b)
+        rep, _ = E.solve(op, P, b, x, E.options(tol=tol, M=M, q_budget_bytes=4000 * p.n * 8))
+        if rep["status"] != "ok":
+            raise RuntimeError(f"training solve {s} did not converge: {rep}")
+        A5.append(torch.from_numpy(a5).to(device))
+        B.append(b)
+        X.append(x)
+        if log and (j + 1) % 64 == 0:
+            log(f"[data] {j + 1}/{len(seeds)} solves, last {rep['iters']} iterations, {time.time() - t0:.1f}s")
+    return torch.stack(A5), torch.stack(B), torch.stack(X)
+
+
+def train(model: LearnedFactor, a5, b, x, epochs=4, batch=16, lr=3e-3, seed=0, log=print):
+    """Adam over shuffled minibatches; returns the mean loss of every epoch."""
+    N = a5.shape[0]
+    rng = np.random.default_rng(seed)
+    hist = []
+    for ep in range(epochs):
+        order = rng.permutation(N)
+        tot, cnt = 0.0, 0
+        for i in range(0, N - batch + 1, batch):
+            idx = model.torch.from_numpy(order[i:i + batch]).to(a5.device)
+            loss = model.train_step(a5.index_select(0, idx), b.index_select(0, idx), x.index_select(0, idx), lr)
+            tot += float(loss.sum())
+            cnt += batch
+        hist.append(tot / max(cnt, 1))
+        if log:
+            log(f"[train] epoch {ep + 1}/{epochs} mean loss {hist[-1]:.5f}")
+    return hist
+
+
+def evaluate(model: LearnedFactor, seeds, device, scale=1, kinds=("learned", "jacobi", "bj_ic0", "plain"),
+             kmax=4000, params_jacobi=None):
+    """Iterations and seconds of ECG (t = 16, FP64, tol 1e-8) per preconditioner kind."""
+    import torch
+
+    out = {k: [] for k in kinds}
+    jac = None
+    if "jacobi" in kinds:
+        jac = LearnedFactor(model.nx, model.ny, params_jacobi, device)
+    for s in seeds:
+        p, a5 = family(s, scale)
+        op = E.Operator.from_csr(p.A)
+        P = E.Partition(p.part, p.t)
+        bt = torch.from_numpy(p.b).to(device)
+        a5t = torch.from_numpy(a5).to(device)[None]
+        for k in kinds:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if k == "learned":
+                M = model.preconditioner(a5t)
+            elif k == "jacobi":
+                M = jac.preconditioner(a5t)
+            elif k == "bj_ic0":
+                M = E.Precond.bj_ic0(op, P)
+            else:
+                M = None
+            torch.cuda.synchronize()
+            setup = time.perf_counter() - t0
+            x = torch.zeros_like(bt)
+            opts = E.options(tol=p.tol, kmax=kmax, M=M, q_budget_bytes=min(kmax, 4000) * p.t * p.n * 8)
+            rep, _ = E.solve(op, P, bt, x, opts)
+            out[k].append({"seed": s, "iters": rep["iters"], "seconds": rep["seconds"], "setup_s": setup,
+                           "relres_true": rep["relres_true"], "status": rep["status"]})
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train", type=int, default=256, help="training operators (seeds 0..N-1)")
+    ap.add_argument("--heldout", type=int, default=16, help="held-out operators (seeds 2000..)")
+    ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--scale", type=int, default=1)
+    ap.add_argument("--init-seed", type=int, default=0)
+    ap.add_argument("--plain", action="store_true", help="also evaluate unpreconditioned ECG")
+    ap.add_argument("--out", default="")
+    args = ap.parse_args()
+
+    import torch
+
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+    p0, _ = family(0, args.scale)
+    nx, ny = p0.grid
+    theta0 = W.init_params(args.init_seed)
+    model = LearnedFactor(nx, ny, theta0, dev)
+    t0 = time.time()
+    a5, b, x = solve_dataset(range(args.train), dev, args.scale, log=log)
+    t_data = time.time() - t0
+    torch.cuda.synchronize()
+    t0 = time.time()
+    hist = train(model, a5, b, x, args.epochs, args.batch, args.lr, log=log)
+    torch.cuda.synchronize()
+    t_train = time.time() - t0
+    kinds = ("learned", "jacobi", "bj_ic0") + (("plain",) if args.plain else ())
+    res = evaluate(model, range(2000, 2000 + args.heldout), dev, args.scale, kinds, params_jacobi=theta0)
+    summary = {k: {"mean_iters": float(np.mean([r["iters"] for r in v])),
+                   "mean_seconds": float(np.mean([r["seconds"] for r in v])),
+                   "mean_setup_s": float(np.mean([r["setup_s"] for r in v])),
+                   "max_relres_true": float(np.max([r["relres_true"] for r in v])),
+                   "all_ok": all(r["status"] == "ok" for r in v)} for k, v in res.items()}
+    out = {"train_ops": args.train, "heldout_ops": args.heldout, "epochs": args.epochs, "batch": args.batch,
+           "lr": args.lr, "data_seconds": t_data, "train_seconds": t_train, "loss_per_epoch": hist,
+           "summary": summary, "params": model.params.cpu().numpy().astype(float).tolist()}
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump(out, f)
+    out.pop("params")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

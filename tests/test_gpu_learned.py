@@ -1,0 +1,168 @@
+"""GPU parity of the learned preconditioner kernels (through the C ABI) against the FP64
+oracle in oracle/learned.py, and a check that training helps.
+
+Tolerances: the network runs in FP32 on the GPU (weights, activations), so G and the
+parameter gradient agree with the FP64 oracle to ~1e-5 relative; the loss and dL/dG are
+FP64 on both sides (1e-12 given the same G); the CSR of G is exact.
+"""
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import ecg as ora
+from oracle import learned as Lr
+from oracle import precond as opre
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible GPU")
+    from paper_2305_19013_amd import learned
+
+    learned._lib()
+    return torch, torch.device("cuda:0"), learned
+
+
+def _batch(seeds, scale=8):
+    ps, a5s, xs = [], [], []
+    for s in seeds:
+        p = W.config("learn2d256", seed=s, scale=scale)  # 32x32 grid
+        a5 = W.stencil5(p.A, p.grid[0])
+        x = np.linalg.solve(p.A.to_scipy().toarray(), p.b)
+        ps.append(p)
+        a5s.append(a5)
+        xs.append(x)
+    return ps, np.stack(a5s), np.stack([p.b for p in ps]), np.stack(xs)
+
+
+def _theta(seed=3):
+    th = W.init_params(seed)
+    rng = np.random.default_rng(seed + 100)
+    return th + 0.05 * rng.standard_normal(th.shape)
+
+
+def test_forward_matches_oracle(env):
+    torch, dev, learned = env
+    ps, a5, b, x = _batch([1, 2, 3])
+    nx, ny = ps[0].grid
+    th = _theta()
+    m = learned.LearnedFactor(nx, ny, th, dev)
+    g3 = m.forward(torch.from_numpy(a5).to(dev)).cpu().numpy()
+    th32 = np.asarray(th, dtype=np.float32).astype(np.float64)  # the GPU holds FP32 parameters
+    for s in range(3):
+        o, _ = Lr.mlp_forward(th32, Lr.features(a5[s], nx))
+        ref = np.stack(Lr.g_diagonals(o, a5[s], nx))
+        assert np.abs(g3[s] - ref).max() <= 2e-5 * np.abs(ref).max()
+
+
+def test_loss_grad_matches_oracle(env):
+    torch, dev, learned = env
+    ps, a5, b, x = _batch([4, 5])
+    nx, ny = ps[0].grid
+    rng = np.random.default_rng(0)
+    g3 = []
+    for s in range(2):
+        o = 0.1 * rng.standard_normal((ps[s].n, 3))
+        g3.append(np.stack(Lr.g_diagonals(o, a5[s], nx)))
+    g3 = np.stack(g3)
+    m = learned.LearnedFactor(nx, ny, W.init_params(0), dev)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    loss, dg3 = m.loss_grad(T(a5), T(g3), T(b), T(x))
+    loss, dg3 = loss.cpu().numpy(), dg3.cpu().numpy()
+    for s in range(2):
+        A = ps[s].A.to_scipy()
+        L, dg = Lr.loss_and_grad_g(A, Lr.g_matrix(*g3[s], nx), b[s], x[s], nx)
+        assert abs(loss[s] - L) <= 1e-12 * abs(L)
+        for k in range(3):
+            assert np.abs(dg3[s][k] - dg[k]).max() <= 1e-11 * np.abs(dg[k]).max() + 1e-300
+
+
+def test_backward_and_adam_match_oracle(env):
+    torch, dev, learned = env
+    ps, a5, b, x = _batch([6, 7, 8, 9])
+    nx, ny = ps[0].grid
+    th = np.asarray(_theta(5), dtype=np.float32).astype(np.float64)
+    m = learned.LearnedFactor(nx, ny, th, dev)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    g3 = m.forward(T(a5))
+    loss, dg3 = m.loss_grad(T(a5), g3, T(b), T(x))
+    grad = m.backward(T(a5), dg3, 0.25).cpu().numpy()
+    ops = [(ps[s].A.to_scipy(), a5[s], b[s], x[s]) for s in range(4)]
+    Lref, gref = Lr.batch_loss_and_grad(th, ops, nx)
+    assert abs(float(loss.mean()) - Lref) <= 1e-5 * abs(Lref)
+    assert np.linalg.norm(grad - gref) <= 2e-4 * np.linalg.norm(gref)
+    # Adam on the GPU gradient
+    m.adam(lr=1e-2)
+    th1, _, _ = Lr.adam_step(th, grad, np.zeros_like(th), np.zeros_like(th), 1, lr=1e-2)
+    assert np.abs(m.params.cpu().numpy() - th1).max() <= 1e-6
+
+
+def test_factor_csr_is_exact(env):
+    torch, dev, learned = env
+    ps, a5, b, x = _batch([10])
+    nx, ny = ps[0].grid
+    m = learned.LearnedFactor(nx, ny, _theta(7), dev)
+    a5t = torch.from_numpy(a5).to(dev)
+    g3 = m.forward(a5t).cpu().numpy()[0]
+    n = ps[0].n
+    nnz = 3 * n - nx - ny
+    rp = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    ci = torch.empty(nnz, dtype=torch.int32, device=dev)
+    va = torch.empty(nnz, dtype=torch.float64, device=dev)
+    import ctypes as C
+
+    from paper_2305_19013_amd import ecg as E
+
+    E.check(learned._lib().ecg_nn_factor_csr(nx, ny, C.c_void_p(m.forward(a5t).data_ptr()), C.c_void_p(rp.data_ptr()),
+                                             C.c_void_p(ci.data_ptr()), C.c_void_p(va.data_ptr()), E._stream()))
+    G = Lr.g_matrix(*g3, nx)
+    assert np.array_equal(rp.cpu().numpy(), G.indptr) and np.array_equal(ci.cpu().numpy(), G.indices)
+    assert np.array_equal(va.cpu().numpy(), G.data)
+
+
+def test_learned_preconditioned_solve_matches_oracle(env):
+    # ECG with M^{-1} = G G^T from the network, against the oracle with the same G
+    torch, dev, learned = env
+    from paper_2305_19013_amd import ecg as E
+
+    p = W.config("learn2d256", seed=12, scale=4)  # 64x64, t = 16
+    nx, ny = p.grid
+    a5 = W.stencil5(p.A, nx)
+    m = learned.LearnedFactor(nx, ny, _theta(9), dev)
+    a5t = torch.from_numpy(a5).to(dev)[None]
+    g3 = m.forward(a5t).cpu().numpy()[0]
+    G = Lr.g_matrix(*g3, nx)
+    A = p.A.to_scipy()
+    ref = ora.flexible_sre_cg2(A, p.b, p.part, p.t, tol=1e-8, precond=opre.factor_preconditioner(G))
+    M = m.preconditioner(a5t)
+    op = E.Operator.from_csr(p.A)
+    P = E.Partition(p.part, p.t)
+    bt = torch.from_numpy(p.b).to(dev)
+    xt = torch.zeros_like(bt)
+    rep, _ = E.solve(op, P, bt, xt, E.options(tol=1e-8, M=M))
+    assert rep["iters"] == ref.it
+    assert np.linalg.norm(xt.cpu().numpy() - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
+
+
+def test_training_lowers_loss_and_iterations(env):
+    """A short training run on 32 operators of a 64x64 family: the loss falls and the
+    trained G needs fewer ECG iterations than its Jacobi start on held-out operators."""
+    torch, dev, learned = env
+    p0 = W.config("learn2d256", seed=0, scale=4)
+    nx, ny = p0.grid
+    th0 = W.init_params(0)
+    m = learned.LearnedFactor(nx, ny, th0, dev)
+    a5, b, x = learned.solve_dataset(range(32), dev, scale=4, log=None)
+    hist = learned.train(m, a5, b, x, epochs=12, batch=8, lr=3e-3, log=None)
+    assert hist[-1] < 0.9 * hist[0]
+    res = learned.evaluate(m, range(2000, 2004), dev, scale=4, kinds=("learned", "jacobi"), params_jacobi=th0)
+    it_l = np.mean([r["iters"] for r in res["learned"]])
+    it_j = np.mean([r["iters"] for r in res["jacobi"]])
+    assert all(r["status"] == "ok" for r in res["learned"])
+    assert it_l < it_j, (it_l, it_j)

@@ -288,3 +288,92 @@ def test_block_jacobi_commutes_with_split():
     lhs = pre.linvT(ecg.split(pre.linv(r), p.part >> 1, p.t // 2))
     rhs = pre.minv(ecg.split(r, p.part >> 1, p.t // 2))
     assert np.abs(lhs - rhs).max() <= 1e-12 * np.abs(rhs).max()
+
+
+# ---------------------------------------------------------------- learned G G^T (oracle)
+def _learn_case(seed=3, scale=16):
+    from oracle import learned as Lr
+
+    p = W.config("learn2d256", seed=seed, scale=scale)  # 16x16 grid
+    A = p.A.to_scipy()
+    nx = p.grid[0]
+    a5 = Lr.stencil5(A, nx)
+    x = np.linalg.solve(A.toarray(), p.b)
+    return p, A, nx, a5, x
+
+
+def test_learned_zero_output_is_jacobi_and_spd():
+    from oracle import learned as Lr
+
+    p, A, nx, a5, x = _learn_case()
+    o = np.zeros((p.n, 3))
+    G = Lr.g_matrix(*Lr.g_diagonals(o, a5, nx), nx).toarray()
+    assert np.allclose(G @ G.T, np.diag(1.0 / A.diagonal()), rtol=1e-14, atol=0)
+    theta = Lr.init_params(5)
+    theta[-99:] = 0.05 * np.random.default_rng(1).standard_normal(99)  # non-zero last layer
+    o, _ = Lr.mlp_forward(theta, Lr.features(a5, nx))
+    G = Lr.g_matrix(*Lr.g_diagonals(o, a5, nx), nx).toarray()
+    assert np.all(np.diag(G) > 0) and np.allclose(np.triu(G, 1), 0)
+    assert np.linalg.eigvalsh(G @ G.T).min() > 0
+
+
+def test_stencil5_reassembles_operator():
+    from oracle import learned as Lr
+
+    p, A, nx, a5, x = _learn_case(seed=4)
+    n = p.n
+    v = np.random.default_rng(2).standard_normal(n)
+    y = a5[0] * v
+    y[1:] += a5[1][1:] * v[:-1]
+    y[:-1] += a5[2][:-1] * v[1:]
+    y[nx:] += a5[3][nx:] * v[:-nx]
+    y[:-nx] += a5[4][:-nx] * v[nx:]
+    assert np.allclose(y, A @ v, rtol=1e-14, atol=1e-12 * np.abs(A @ v).max())
+
+
+def test_learned_gradient_matches_finite_differences():
+    # central differences of the batch loss in random parameter directions (FP64)
+    from oracle import learned as Lr
+
+    p, A, nx, a5, x = _learn_case(seed=6)
+    rng = np.random.default_rng(7)
+    theta = Lr.init_params(8)
+    theta += 0.05 * rng.standard_normal(theta.shape)
+    ops = [(A, a5, p.b, x)]
+    L0, g = Lr.batch_loss_and_grad(theta, ops, nx)
+    for _ in range(4):
+        d = rng.standard_normal(theta.shape)
+        h = 1e-5
+        Lp, _ = Lr.batch_loss_and_grad(theta + h * d, ops, nx)
+        Lm, _ = Lr.batch_loss_and_grad(theta - h * d, ops, nx)
+        fd = (Lp - Lm) / (2 * h)
+        assert abs(fd - g @ d) <= 1e-6 * max(abs(fd), 1e-3)
+
+
+def test_learned_g_gradient_matches_finite_differences():
+    # the closed-form dL/dG_ij = (2/c)((Ae)_i u_j + b_i w_j) against differences of L
+    from oracle import learned as Lr
+
+    p, A, nx, a5, x = _learn_case(seed=9)
+    rng = np.random.default_rng(3)
+    o = 0.1 * rng.standard_normal((p.n, 3))
+    gd, gw, gs = Lr.g_diagonals(o, a5, nx)
+    L, (dgd, dgw, dgs) = Lr.loss_and_grad_g(A, Lr.g_matrix(gd, gw, gs, nx), p.b, x, nx)
+    for arr, darr in ((gd, dgd), (gw, dgw), (gs, dgs)):
+        for j in rng.choice(np.nonzero(arr)[0], 5, replace=False):
+            h = 1e-6 * max(abs(arr[j]), 1e-3)
+            arr[j] += h
+            Lp, _ = Lr.loss_and_grad_g(A, Lr.g_matrix(gd, gw, gs, nx), p.b, x, nx)
+            arr[j] -= 2 * h
+            Lm, _ = Lr.loss_and_grad_g(A, Lr.g_matrix(gd, gw, gs, nx), p.b, x, nx)
+            arr[j] += h
+            assert abs((Lp - Lm) / (2 * h) - darr[j]) <= 1e-5 * max(abs(darr[j]), 1e-8) + 1e-9
+
+
+def test_adam_first_step_is_signed_learning_rate():
+    # with bias correction the first Adam step moves every coordinate by lr * g/(|g|+eps)
+    from oracle import learned as Lr
+
+    g = np.array([0.3, -2.0, 1e-3, 0.0])
+    th, m, v = Lr.adam_step(np.zeros(4), g, np.zeros(4), np.zeros(4), 1, lr=0.01)
+    assert np.allclose(th, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=0)

@@ -17,3 +17,4 @@ from .diffusion import (  # noqa: F401
 from .partition import box_partition, morton_box_ids, random_partition  # noqa: F401
 from .dense import random_spd, dense_to_csr  # noqa: F401
 from .configs import Problem, config, CONFIG_NAMES  # noqa: F401
+from .nn_inputs import stencil5, init_params, NPARAM  # noqa: F401
