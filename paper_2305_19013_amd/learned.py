@@ -4,8 +4,9 @@ Everything numerical runs in libecg.so: the network forward/backward, the loss a
 gradient, Adam, the CSR of G, and the ECG solves that produce the training solutions.
 This module only moves arguments, picks minibatches and loops.
 
-Usage (trains on operators of the learn2d256 family and evaluates on held-out seeds):
-    python -m paper_2305_19013_amd.learned --train 256 --heldout 16 --epochs 4
+Usage (trains on operators 0..N-1 of the learn2d256 family, keeps the epoch with the fewest
+ECG iterations on validation seeds 1900.., evaluates on held-out seeds 2000..):
+    python -m paper_2305_19013_amd.learned --train 2000 --heldout 200 --epochs 40
 """
 
 from __future__ import annotations
@@ -154,11 +155,19 @@ def solve_dataset(seeds, device, scale=1, tol=1e-10, log=print):
     return torch.stack(A5), torch.stack(B), torch.stack(X)
 
 
-def train(model: LearnedFactor, a5, b, x, epochs=4, batch=16, lr=3e-3, seed=0, log=print):
-    """Adam over shuffled minibatches; returns the mean loss of every epoch."""
+def train(model: LearnedFactor, a5, b, x, epochs=4, batch=16, lr=3e-3, seed=0, log=print, val_seeds=(),
+          val_scale=1, val_every=5):
+    """Adam over shuffled minibatches; returns the mean loss of every epoch.
+
+    With val_seeds, every val_every epochs the mean ECG iteration count on those validation
+    operators is measured and the parameters with the fewest iterations are kept (the
+    loss follows iteration counts only loosely, so training stops early on them)."""
     N = a5.shape[0]
     rng = np.random.default_rng(seed)
     hist = []
+    best = (float("inf"), model.params.clone(), 0)
+    if val_seeds:
+        best = (_val_iters(model, val_seeds, a5.device, val_scale), model.params.clone(), 0)
     for ep in range(epochs):
         order = rng.permutation(N)
         tot, cnt = 0.0, 0
@@ -168,9 +177,25 @@ def train(model: LearnedFactor, a5, b, x, epochs=4, batch=16, lr=3e-3, seed=0, l
             tot += float(loss.sum())
             cnt += batch
         hist.append(tot / max(cnt, 1))
+        msg = f"[train] epoch {ep + 1}/{epochs} mean loss {hist[-1]:.5f}"
+        if val_seeds and ((ep + 1) % val_every == 0 or ep + 1 == epochs):
+            it = _val_iters(model, val_seeds, a5.device, val_scale)
+            msg += f" validation iterations {it:.1f}"
+            if it < best[0]:
+                best = (it, model.params.clone(), ep + 1)
         if log:
-            log(f"[train] epoch {ep + 1}/{epochs} mean loss {hist[-1]:.5f}")
+            log(msg)
+    if val_seeds:
+        model.params.copy_(best[1])
+        model.best_epoch, model.best_val_iters = best[2], best[0]
+        if log:
+            log(f"[train] kept the parameters of epoch {best[2]} ({best[0]:.1f} validation iterations)")
     return hist
+
+
+def _val_iters(model, seeds, device, scale):
+    res = evaluate(model, seeds, device, scale, kinds=("learned",))
+    return float(np.mean([r["iters"] for r in res["learned"]]))
 
 
 def evaluate(model: LearnedFactor, seeds, device, scale=1, kinds=("learned", "jacobi", "bj_ic0", "plain"),
@@ -219,6 +244,8 @@ def main():
     ap.add_argument("--scale", type=int, default=1)
     ap.add_argument("--init-seed", type=int, default=0)
     ap.add_argument("--plain", action="store_true", help="also evaluate unpreconditioned ECG")
+    ap.add_argument("--val", type=int, default=4, help="validation operators (seeds 1900..)")
+    ap.add_argument("--val-every", type=int, default=5)
     ap.add_argument("--out", default="")
     args = ap.parse_args()
 
@@ -237,7 +264,8 @@ def main():
     t_data = time.time() - t0
     torch.cuda.synchronize()
     t0 = time.time()
-    hist = train(model, a5, b, x, args.epochs, args.batch, args.lr, log=log)
+    hist = train(model, a5, b, x, args.epochs, args.batch, args.lr, log=log,
+                 val_seeds=tuple(range(1900, 1900 + args.val)), val_scale=args.scale, val_every=args.val_every)
     torch.cuda.synchronize()
     t_train = time.time() - t0
     kinds = ("learned", "jacobi", "bj_ic0") + (("plain",) if args.plain else ())
@@ -248,6 +276,7 @@ def main():
                    "max_relres_true": float(np.max([r["relres_true"] for r in v])),
                    "all_ok": all(r["status"] == "ok" for r in v)} for k, v in res.items()}
     out = {"train_ops": args.train, "heldout_ops": args.heldout, "epochs": args.epochs, "batch": args.batch,
+           "best_epoch": getattr(model, "best_epoch", None), "val_ops": args.val,
            "lr": args.lr, "data_seconds": t_data, "train_seconds": t_train, "loss_per_epoch": hist,
            "summary": summary, "params": model.params.cpu().numpy().astype(float).tolist()}
     if args.out:

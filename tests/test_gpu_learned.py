@@ -151,16 +151,18 @@ def test_learned_preconditioned_solve_matches_oracle(env):
 
 
 def test_training_lowers_loss_and_iterations(env):
-    """A short training run on 32 operators of a 64x64 family: the loss falls and the
-    trained G needs fewer ECG iterations than its Jacobi start on held-out operators."""
+    """A short training run on 32 operators of a 64x64 family (checkpoint chosen by ECG
+    iterations on 3 validation operators): the loss falls and the trained G needs fewer ECG
+    iterations than its Jacobi start on 4 held-out operators."""
     torch, dev, learned = env
     p0 = W.config("learn2d256", seed=0, scale=4)
     nx, ny = p0.grid
     th0 = W.init_params(0)
     m = learned.LearnedFactor(nx, ny, th0, dev)
     a5, b, x = learned.solve_dataset(range(32), dev, scale=4, log=None)
-    hist = learned.train(m, a5, b, x, epochs=12, batch=8, lr=3e-3, log=None)
-    assert hist[-1] < 0.9 * hist[0]
+    hist = learned.train(m, a5, b, x, epochs=40, batch=8, lr=3e-3, log=None, val_seeds=(1900, 1901, 1902),
+                         val_scale=4, val_every=5)
+    assert min(hist) < 0.9 * hist[0]
     res = learned.evaluate(m, range(2000, 2004), dev, scale=4, kinds=("learned", "jacobi"), params_jacobi=th0)
     it_l = np.mean([r["iters"] for r in res["learned"]])
     it_j = np.mean([r["iters"] for r in res["jacobi"]])
