@@ -12,6 +12,9 @@ defined directly rather than through the solver's block recurrences.
   Algorithm 3 builds when it switches: S_1 = span T^t(r_0); a regular step
   adds A times the A-orthogonal complement of S_{k-1} in S_k; a switch step
   adds span T^{t/2}(r_k), with r_k the Galerkin residual on S_k.
+* ``msdo_projection``: the Galerkin iterates of MSDO-CG / modified MSDO-CG, on the
+  modified subspace span{T(r_0), ..., T(r_{k-1})} of Section 2.2 (r_j the Galerkin
+  residual on the previous subspace; after a switch the split uses t/2 merged subdomains).
 * ``cg_iterates``: classical CG in 50 digits (the t = 1 case).
 """
 
@@ -121,6 +124,30 @@ def recursion_projection(A, b, part, t, k_total, switch_iters=(), x0=None):
                 cand = _split(r, np.asarray(part) >> level, t_cur)
             else:
                 cand = Am * newest
+            newest = _a_orth_basis(Am, cand, basis)
+            basis = newest if basis is None else _hcat([basis, newest])
+            x = x0m + basis * (basis.T * r0)
+            r = _mat(b) - Am * x
+            out.append(_to_np(x)[:, 0])
+        return out
+
+
+def msdo_projection(A, b, part, t, k_total, switch_iters=(), x0=None):
+    """Galerkin iterates x_1..x_k_total on S_k = span{T(r_0), ..., T(r_{k-1})}."""
+    switch_iters = set(int(s) for s in switch_iters)
+    with mp.workdps(DPS):
+        Am = _mat(A)
+        x0m = _mat(np.zeros(len(b)) if x0 is None else x0)
+        r0 = _mat(b) - Am * x0m
+        basis = None
+        t_cur, level = t, 0
+        r = r0
+        out = []
+        for k in range(1, k_total + 1):
+            if k in switch_iters:
+                level += 1
+                t_cur //= 2
+            cand = _split(r, np.asarray(part) >> level, t_cur)
             newest = _a_orth_basis(Am, cand, basis)
             basis = newest if basis is None else _hcat([basis, newest])
             x = x0m + basis * (basis.T * r0)

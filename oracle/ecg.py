@@ -28,9 +28,11 @@ What it follows
 
 Readings where the paper is silent (stated again in the design notes):
 * the absolute value in tol1 (the algorithms omit it, the text has it);
-* rank deficiency: a column is dropped (deflated) when, in either QR step,
-  its Schur-complement pivot is <= deflate_tol times its own diagonal entry;
-  a block whose columns are all dropped ends the solve (status "breakdown");
+* rank deficiency: a column is dropped (deflated) when its Schur-complement pivot is
+  <= deflate_tol times a reference: in the Euclidean QR step the column's squared norm
+  before it was A-orthonormalised against the stored blocks, in the A step its own
+  diagonal entry; a block whose columns are all dropped ends the solve (status
+  "breakdown");
 * repeated halving (rule REPEAT) and forced switch iterations (SCHEDULE)
   generalise the paper's single switch.
 
@@ -103,14 +105,17 @@ def _select_columns(gram: np.ndarray, tau: float):
     return keep
 
 
-def euclidean_qr(W: np.ndarray, tau: float):
+def euclidean_qr(W: np.ndarray, tau: float, ref2=None):
     """Thin Householder QR with positive diagonal, dropping dependent columns.
 
     Column j is dropped when its distance to the span of the previously kept
-    columns, squared, is <= tau * ||w_j||^2.  Returns (W_hat, kept indices), or
+    columns, squared, is <= tau * ref2[j] (ref2 defaults to ||w_j||^2; the solver passes
+    the squared norms of the candidate before it was A-orthonormalised against the stored
+    blocks, so a column that lay in their span is dropped even though what is left of it
+    is rounding noise of its own size).  Returns (W_hat, kept indices), or
     (None, None) when tau < 0 and W is numerically rank deficient.
     """
-    nrm2 = np.einsum("ij,ij->j", W, W)
+    nrm2 = np.einsum("ij,ij->j", W, W) if ref2 is None else np.asarray(ref2, dtype=np.float64)
     m = W.shape[1]
     Qh, R = np.linalg.qr(W)
     d2 = np.diag(R) ** 2
@@ -139,27 +144,35 @@ def euclidean_qr(W: np.ndarray, tau: float):
     return Qh * s[None, :], keep
 
 
-def a_orthonormalize_self(W: np.ndarray, A, tau: float):
+def a_orthonormalize_self(W: np.ndarray, A, tau: float, keep_width: bool = False, ref2=None):
     """Pre-CholQR in the A inner product with deflation.
 
-    Returns the A-orthonormal block (n x t_eff) or None on breakdown (tau < 0).
+    Returns the A-orthonormal block (n x t_eff) or None on breakdown (tau < 0).  With
+    keep_width the block keeps its t columns and a dropped column is a zero column in the
+    position of the candidate column it came from (MSDO-CG pairs column j with subdomain j).
     """
-    What, keep = euclidean_qr(W, tau)
+    n, t = W.shape
+    What, keep = euclidean_qr(W, tau, ref2)
     if What is None:
         return None
     if What.shape[1] == 0:
-        return What
+        return np.zeros((n, t)) if keep_width else What
     S = What.T @ (A @ What)
     S = 0.5 * (S + S.T)
     keep2 = _select_columns(S, tau)
     if keep2 is None:
         return None
     if not keep2:
-        return np.zeros((W.shape[0], 0))
+        return np.zeros((n, t)) if keep_width else np.zeros((n, 0))
     S2 = S[np.ix_(keep2, keep2)]
     C = np.linalg.cholesky(S2).T  # upper, S2 = C^T C
     # W = W_hat C^{-1}  <=>  C^T W^T = W_hat^T
-    return sla.solve_triangular(C, What[:, keep2].T, trans="T", lower=False).T
+    Wn = sla.solve_triangular(C, What[:, keep2].T, trans="T", lower=False).T
+    if not keep_width:
+        return Wn
+    full = np.zeros((n, t))
+    full[:, [keep[j] for j in keep2]] = Wn
+    return full
 
 
 def a_orthonormalize_against(W: np.ndarray, Qm: np.ndarray, A) -> np.ndarray:
@@ -277,11 +290,12 @@ def flexible_sre_cg2(A, b, part, t, *, x0=None, tol=1e-8, kmax=20000, reduce=RED
             cand = from_residual(r, level, t_cur)
         else:
             cand = Z_prev if pre is None else pre.minv(Z_prev)
+        ref2 = np.einsum("ij,ij->j", cand, cand)  # column norms before CGS2 (deflation reference)
         if blocks:
             # Q = all stored blocks, or the last `trunc` of them (Section 3)
             first = 0 if trunc <= 0 else colstart[max(len(blocks) - trunc, 0)]
             cand = a_orthonormalize_against(cand, Qbuf[:, first:ncols], A)
-        W = a_orthonormalize_self(cand, A, deflate_tol)
+        W = a_orthonormalize_self(cand, A, deflate_tol, ref2=ref2)
         if W is None or W.shape[1] == 0:
             res.status = "breakdown"
             break
@@ -350,3 +364,86 @@ def true_relres(A, b, x) -> float:
 def memory_formula(t: int, it: int, sit: int) -> int:
     """Stored vectors with one halving at iteration sit+1 (Section 5.2 tables)."""
     return t * sit + (t // 2) * (it - sit)
+
+
+def flexible_msdo_cg(A, b, part, t, *, x0=None, tol=1e-8, kmax=20000, reduce=REDUCE_NONE, switch_tol=1e-5,
+                     t_min=1, min_gap=1, schedule=(), trunc=0, deflate_tol=1e-14,
+                     precond: SplitPreconditioner | None = None, record=False) -> EcgResult:
+    """Flexibly MSDO-CG (Section 4.4, Algorithm 4; Algorithm 2 without a switch; with a
+    split preconditioner, Algorithm 5).
+
+    P_1 = [T^t(r_0)]; at a switch P_k = [T^{t/2}(r_{k-1})]; otherwise
+    P_k = [T(r_{k-1})] + P_{k-1} diag(beta_k) with beta_k = -V_{k-1}^T r_{k-1} and
+    V_{k-1} = A P_{k-1} (eq. (pk)).  P_k is A-orthonormalised against the stored blocks and
+    against itself, then alpha_k = P_k^T r_{k-1}, x_k = x_{k-1} + P_k alpha_k,
+    r_k = r_{k-1} - V_k alpha_k.  Preconditioned (Algorithm 5):
+    beta_k = -V_{k-1}^T (M^{-1} r_{k-1}) and the split term is L^{-T}[T(L^{-1} r_{k-1})].
+    Blocks keep t columns (a deflated column stays a zero column), so column j of P_{k-1}
+    always pairs with subdomain j.
+    """
+    b = np.asarray(b, dtype=np.float64)
+    part = np.asarray(part)
+    n = b.shape[0]
+    x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
+    r = b - A @ x
+    rho0 = float(np.linalg.norm(r))
+    res = EcgResult(x=x, it=0, switch_iters=[], widths=[], rho=[rho0], status="converged",
+                    t_final=t, deflated=0)
+    if rho0 == 0.0:
+        return res
+    schedule = set(int(s) for s in schedule)
+    pre = precond
+    rho_prev, tol1, k, level, t_cur = rho0, 1.0, 1, 0, t
+    blocks = []
+    P_prev = V_prev = None
+
+    def split_term(rv, lvl, width):
+        if pre is None:
+            return split(rv, merged_partition(part, lvl), width)
+        return pre.linvT(split(pre.linv(rv), merged_partition(part, lvl), width))
+
+    while rho_prev > tol * rho0 and k < kmax:
+        if k == 1:
+            cand = split_term(r, 0, t_cur)
+        elif _switch_now(reduce, k, tol1, switch_tol, t_cur, t_min, res.switch_iters, min_gap, schedule):
+            level += 1
+            t_cur //= 2
+            res.switch_iters.append(k)
+            cand = split_term(r, level, t_cur)
+        else:
+            rr = r if pre is None else pre.minv(r)
+            beta = -(V_prev.T @ rr)
+            cand = split_term(r, level, t_cur) + P_prev * beta[None, :]
+        ref2 = np.einsum("ij,ij->j", cand, cand)  # column norms before CGS2 (deflation reference)
+        active = blocks if trunc <= 0 else blocks[-trunc:]
+        if active:
+            cand = a_orthonormalize_against(cand, np.hstack(active), A)
+        P = a_orthonormalize_self(cand, A, deflate_tol, keep_width=True, ref2=ref2)
+        live = 0 if P is None else int(np.count_nonzero(np.any(P != 0.0, axis=0)))
+        if P is None or live == 0:
+            res.status = "breakdown"
+            break
+        V = A @ P
+        alpha = P.T @ r
+        x = x + P @ alpha
+        r = r - V @ alpha
+        rho = float(np.linalg.norm(r))
+        tol1 = abs(rho - rho_prev) / rho0
+        rho_prev = rho
+        res.rho.append(rho)
+        res.widths.append(live)
+        res.deflated += t_cur - live  # every MSDO candidate has t_cur fresh columns
+        blocks.append(P)
+        P_prev, V_prev = P, V
+        if record:
+            res.iterates.append(x.copy())
+            res.residuals.append(r.copy())
+        k += 1
+    res.x = x
+    res.it = k - 1
+    res.t_final = t_cur
+    if res.status != "breakdown" and rho_prev > tol * rho0:
+        res.status = "not_converged"
+    if record:
+        res.blocks = blocks
+    return res

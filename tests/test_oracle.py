@@ -377,3 +377,37 @@ def test_adam_first_step_is_signed_learning_rate():
     g = np.array([0.3, -2.0, 1e-3, 0.0])
     th, m, v = Lr.adam_step(np.zeros(4), g, np.zeros(4), np.zeros(4), 1, lr=0.01)
     assert np.allclose(th, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=0)
+
+
+# ---------------------------------------------------------------- MSDO-CG (Section 2.2, Algorithms 2 and 4)
+def test_msdo_iterates_equal_modified_subspace_projection():
+    # both MSDO-CG and modified MSDO-CG are the Galerkin iterates on span{T(r_0),...,T(r_{k-1})}
+    A, b, part = tiny(n=40, t=4, kappa=30.0, seed=41)
+    xs = brute.msdo_projection(A, b, part, 4, 6)
+    ms = ecg.flexible_msdo_cg(A, b, part, 4, tol=1e-14, kmax=7, record=True)
+    mm = ecg.flexible_sre_cg2(A, b, part, 4, tol=1e-14, kmax=7, record=True, candidate="modified-msdo")
+    for k in range(6):
+        assert np.linalg.norm(ms.iterates[k] - xs[k]) <= 1e-11 * np.linalg.norm(xs[k])
+        assert np.linalg.norm(mm.iterates[k] - xs[k]) <= 1e-11 * np.linalg.norm(xs[k])
+
+
+def test_flexible_msdo_iterates_with_switch():
+    A, b, part = tiny(n=40, t=8, kappa=30.0, seed=43)
+    xs = brute.msdo_projection(A, b, part, 8, 6, [3])
+    ms = ecg.flexible_msdo_cg(A, b, part, 8, tol=1e-14, kmax=7, record=True, reduce=ecg.REDUCE_SCHEDULE,
+                              schedule=[3])
+    # a column can be dependent (a subdomain with a single unknown gives parallel splits)
+    assert ms.switch_iters == [3] and ms.widths[0] == 8 and max(ms.widths[2:6]) <= 4
+    for k in range(6):
+        assert np.linalg.norm(ms.iterates[k] - xs[k]) <= 1e-11 * np.linalg.norm(xs[k])
+
+
+def test_msdo_a_orthonormal_and_memory():
+    p = W.config("poisson64")
+    A = p.A.to_scipy()
+    r = ecg.flexible_msdo_cg(A, p.b, p.part, p.t, tol=1e-8, reduce=ecg.REDUCE_ONCE, switch_tol=1e-4, t_min=2,
+                             record=True)
+    assert r.status == "converged" and len(r.switch_iters) == 1
+    assert r.mem == ecg.memory_formula(p.t, r.it, r.sit)
+    Q = np.hstack([B[:, np.any(B != 0, axis=0)] for B in r.blocks[:20]])
+    assert np.abs(Q.T @ (A @ Q) - np.eye(Q.shape[1])).max() <= 1e-10
