@@ -19,6 +19,8 @@ Reported:
   roofline       the kernel class with the most time in the FP64 step: algorithmic bytes
                  per launch / HIP-event launch time, against 8 TB/s HBM
   jump2d512_bj   jump2d512 with block-Jacobi IC(0), FP64 and FP32-refined
+  learn2d256_learned  ECG with the trained G G^T vs its Jacobi start, block-Jacobi IC(0) and
+                 no preconditioner on held-out 256x256 jumping-coefficient operators
   cpu_baseline   the FP64 oracle on the host (bounded sample, extrapolated; see 'sample')
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--t T]
@@ -194,6 +196,39 @@ def cpu_baseline(prob, widths_gpu, it_gpu, switch_gpu, k1=2, k2=6):
             "measured_sample_s": round(ta + tb, 2)}
 
 
+def learned_section(args, torch, dev):
+    """learn2d256 (256x256, log10 k ~ U(-3,3) on 16x16-cell blocks, t = 16): ECG with the
+    trained G G^T against its untrained Jacobi start, block-Jacobi IC(0) and no
+    preconditioner, on held-out operator seeds 2000.. (FP64, tol 1e-8).  The parameters were
+    trained on the GPU by `python -m paper_2305_19013_amd.learned` and are read from
+    paper_2305_19013_amd/trained/learn2d256.json."""
+    import workloads as W
+    from paper_2305_19013_amd import learned as LN
+
+    path = os.path.join(ROOT, "paper_2305_19013_amd", "trained", "learn2d256.json")
+    if not os.path.exists(path):
+        return None
+    meta = json.load(open(path))
+    p0, _ = LN.family(0)
+    nx, ny = p0.grid
+    model = LN.LearnedFactor(nx, ny, np.asarray(meta["params"]), dev)
+    seeds = list(range(2000, 2000 + args.learned_ops))
+    kinds = ("learned", "jacobi", "bj_ic0")
+    LN.evaluate(model, seeds[:1], dev, 1, kinds, params_jacobi=W.init_params(meta["init_seed"]))  # priming
+    res = LN.evaluate(model, seeds, dev, 1, kinds, params_jacobi=W.init_params(meta["init_seed"]))
+    res.update(LN.evaluate(model, seeds[:1], dev, 1, ("plain",), kmax=6000))
+    out = {"train_ops": meta["train_ops"], "epochs": meta["epochs"], "best_epoch": meta.get("best_epoch"),
+           "heldout_ops": len(seeds)}
+    for k, v in res.items():
+        out[k] = {"mean_iters": float(np.mean([r["iters"] for r in v])),
+                  "mean_seconds": round(float(np.mean([r["seconds"] for r in v])), 4),
+                  "mean_setup_seconds": round(float(np.mean([r["setup_s"] for r in v])), 4),
+                  "max_relres_true": float(np.max([r["relres_true"] for r in v])),
+                  "all_converged": all(r["status"] == "ok" for r in v), "ops": len(v)}
+        log(f"[learn2d256 {k}] {out[k]}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -208,6 +243,8 @@ def main():
     ap.add_argument("--progress", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-side", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--learned-ops", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="copy 1 GiB device-to-device before the solves (HBM counter calibration)")
     args = ap.parse_args()
@@ -295,6 +332,8 @@ def main():
             side[f] = {"seconds": round(Rj["seconds"], 4), "iters": rj["iters"], "switch_iters": rj["switch_iters"],
                        "outer_iters": rj["outer_iters"], "relres_true": rj["relres_true"], "status": rj["status"]}
         out["jump2d512_bj"] = side
+    if not args.no_side and not args.no_learned:
+        out["learn2d256_learned"] = learned_section(args, torch, dev)
     if not args.no_cpu:
         # widths history of the GPU run is reconstructed from its report
         it = rep["iters"]

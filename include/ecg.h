@@ -2,7 +2,8 @@
  * ecg.h - C ABI of the MI355X (gfx950) flexibly enlarged Conjugate Gradient solver.
  *
  * The method is flexibly SRE-CG2 (Section 4.3, Algorithm 3 of "Flexibly Enlarged
- * Conjugate Gradient methods"): the residual is split over t subdomains
+ * Conjugate Gradient methods"; MSDO-CG, Algorithms 2, 4 and 5, is a variant): the
+ * residual is split over t subdomains
  * (operator T^t, eq. (Tt)); every iteration adds a block of t search vectors that is
  * A-orthonormalised against the stored blocks (CGS2) and against itself (Pre-CholQR,
  * Section 5); x and r follow the short recurrences of Algorithm 1; once the relative
@@ -64,6 +65,13 @@ typedef enum {
 } ecg_precision;
 
 typedef enum {
+  ECG_SRE_CG2 = 0,         /* next block A W_{k-1} (Algorithms 1 and 3) */
+  ECG_MSDO_CG = 1,         /* next block [T(r_{k-1})] + P_{k-1} diag(beta_k),
+                              beta_k = -V_{k-1}^T r_{k-1} (Algorithms 2, 4 and 5) */
+  ECG_MODIFIED_MSDO = 2    /* next block [T(r_{k-1})] (modified MSDO-CG, Section 2.2) */
+} ecg_variant;
+
+typedef enum {
   ECG_PRECOND_NONE = 0,
   ECG_PRECOND_SPLIT = 1  /* split preconditioner M = L L^T given as an ecg_precond
                             (Section 4.5, option 2, eq. (zsre2)) */
@@ -97,11 +105,15 @@ typedef struct {
                               kmax-1 blocks of width t (or trunc blocks).  Blocks are packed
                               by their width; when the next one does not fit, the oldest
                               are dropped (truncation to the blocks that fit). */
-  double deflate_tol;      /* drop a column whose Cholesky pivot <= deflate_tol times its
-                              diagonal entry; < 0 disables deflation (then a non-positive
-                              pivot is ECG_EBREAKDOWN) */
+  double deflate_tol;      /* drop a column whose Cholesky pivot <= deflate_tol times a
+                              reference: its squared norm before the A-orthonormalisation
+                              against the stored blocks (Euclidean step), its own diagonal
+                              entry (A step); < 0 disables deflation (then a non-positive
+                              pivot is ECG_EBREAKDOWN).  A dropped column stays a zero
+                              column of the block. */
   int32_t precond;         /* ecg_precond_kind */
   const ecg_precond* M;    /* used when precond == ECG_PRECOND_SPLIT */
+  int32_t variant;         /* ecg_variant */
 } ecg_options;
 
 typedef struct {
@@ -123,7 +135,7 @@ typedef struct {
 
 /* Fill *o with defaults: tol 1e-8, kmax 20000, no reduction, switch_tol 1e-5, t_min 1,
  * min_gap 1, FP64, inner_tol 1e-4, max_outer 20, replace_every 0, trunc 0,
- * q_budget_bytes 0, deflate_tol 1e-14, no preconditioner. */
+ * q_budget_bytes 0, deflate_tol 1e-14, no preconditioner, SRE-CG2. */
 ecg_status ecg_options_default(ecg_options* o);
 
 /* Sparse SPD matrix A (n x n) in CSR form, copied to the device.

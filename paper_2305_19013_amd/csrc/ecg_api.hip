@@ -122,7 +122,7 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 struct Plan {
   int n = 0, t0 = 0, t0p = 0, elt = 8;
   long long cap = 0;  // stored-block arena capacity, in columns of n values
-  size_t off_status = 0, off_small_part = 0, off_small_out = 0, off_rinv = 0, off_cinv = 0, off_beta = 0,
+  size_t off_status = 0, off_small_part = 0, off_small_out = 0, off_ref = 0, off_rinv = 0, off_cinv = 0, off_beta = 0,
          off_norm_part = 0, off_scalar = 0, off_gram_part = 0, off_G = 0, off_C = 0, off_Y = 0, off_H = 0,
          off_r = 0, off_r64 = 0, off_d = 0, off_v1 = 0, off_v2 = 0, off_Q = 0, total = 0;
   size_t gram_part_cap = 0;  // elements of T
@@ -159,6 +159,7 @@ ecg_status make_plan(int64_t n, int t, const ecg_options& o, Plan* p) {
   p->off_status = take(sizeof(IterStatus));
   p->off_small_part = take(((size_t)kSmallChunks + 32) * small_len * 8);  // chunks + stage-2 rows
   p->off_small_out = take(small_len * 8);
+  p->off_ref = take(small_len * 8);  // candidate Gram before CGS2 / MSDO's V^T r
   p->off_rinv = take((size_t)tp * tp * 8);
   p->off_cinv = take((size_t)tp * tp * 8);
   p->off_beta = take((size_t)tp * 8);
@@ -197,6 +198,7 @@ ecg_status check_options(const ecg_options* o) {
   if (o->trunc < 0 || o->q_budget_bytes < 0 || o->replace_every < 0) return fail(ECG_EINVAL, "negative size option");
   if (o->precond != ECG_PRECOND_NONE && o->precond != ECG_PRECOND_SPLIT) return fail(ECG_EINVAL, "unknown precond");
   if (o->precond == ECG_PRECOND_SPLIT && !o->M) return fail(ECG_EINVAL, "precond SPLIT needs M");
+  if (o->variant < ECG_SRE_CG2 || o->variant > ECG_MODIFIED_MSDO) return fail(ECG_EINVAL, "unknown variant");
   return ECG_OK;
 }
 
@@ -320,6 +322,7 @@ ecg_status ecg_inner(const ecg_operator* Aop, const ecg_partition* P, const ecg_
   IterStatus* st = reinterpret_cast<IterStatus*>(ws + pl.off_status);
   double* small_part = reinterpret_cast<double*>(ws + pl.off_small_part);
   double* small_out = reinterpret_cast<double*>(ws + pl.off_small_out);
+  double* refg = reinterpret_cast<double*>(ws + pl.off_ref);
   double* Rinv = reinterpret_cast<double*>(ws + pl.off_rinv);
   double* Cinv = reinterpret_cast<double*>(ws + pl.off_cinv);
   double* beta = reinterpret_cast<double*>(ws + pl.off_beta);
@@ -364,13 +367,30 @@ ecg_status ecg_inner(const ecg_operator* Aop, const ecg_partition* P, const ecg_
       res->switches.push_back(k);
       from_r = true;
     }
-    if (from_r) {
+    if (o.variant == ECG_MODIFIED_MSDO) from_r = true;
+    const bool msdo = (o.variant == ECG_MSDO_CG) && !from_r;
+    if (msdo) {
+      // beta_k = -V_{k-1}^T (M^{-1}) r_{k-1}; Cb holds V_{k-1} = A P_{k-1}
+      const T* rr = r;
+      if (M) {
+        precond_apply<T>(M, 0, 1, r, Yb, s);
+        precond_apply<T>(M, 1, 1, Yb, Hb, s);  // M^{-1} r (n x 1)
+        rr = Hb;
+      }
+      launch_small_gram<T>(n, tc, Cb, Cb, rr, small_part, refg, s);  // refg[tc*tc..] = V^T rr
+    }
+    if (from_r || msdo) {
+      T* dst = msdo ? Yb : Cb;  // MSDO: the split term goes next to P_{k-1} first
       if (M) {
         precond_apply<T>(M, 0, 1, r, Yb, s);  // L^{-1} r (n x 1)
         launch_split_t<T>(n, P->part, level, tc, Yb, Hb, s);
-        precond_apply<T>(M, 1, tc, Hb, Cb, s);
+        precond_apply<T>(M, 1, tc, Hb, dst, s);
       } else {
-        launch_split_t<T>(n, P->part, level, tc, r, Cb, s);
+        launch_split_t<T>(n, P->part, level, tc, r, dst, s);
+      }
+      if (msdo) {
+        const QBlock& last = q.blocks.back();
+        launch_msdo_combine<T>(n, tc, Yb, Qbase + (size_t)last.off * n, refg + (size_t)tc * tc, Cb, s);
       }
     } else if (M) {
       precond_apply<T>(M, 0, tc, Cb, Yb, s);  // Cb holds Z_{k-1} = A W_{k-1}
@@ -379,6 +399,8 @@ ecg_status ecg_inner(const ecg_operator* Aop, const ecg_partition* P, const ecg_
     // ---- CGS2 against the stored blocks
     const int m = build_spans<T>(q, o.trunc, Qbase, n, spans);
     if (m > 0) {
+      // squared column norms before CGS2: the reference of the deflation test
+      launch_small_gram<T>(n, tc, Cb, Cb, nullptr, small_part, refg, s);
       for (int pass = 0; pass < 2; ++pass) {
         launch_spmm<T>(A, tc, Cb, Yb, s);
         launch_gram<T>(n, spans.data(), (int)spans.size(), m, tc, Yb, G, gram_part, pl.gram_part_cap, s);
@@ -392,7 +414,7 @@ ecg_status ecg_inner(const ecg_operator* Aop, const ecg_partition* P, const ecg_
     launch_small_gram<T>(n, tc, Cb, Cb, nullptr, small_part, small_out, s);
     stat_end(kStatSmallGram, w * n * 2 * tc, 2.0 * n * tc * tc, s);
     stat_begin(s);
-    launch_factor(0, tc, tl, small_out, tau, Rinv, nullptr, st, s);
+    launch_factor(0, tc, tl, small_out, m > 0 ? refg : nullptr, tau, Rinv, nullptr, st, s);
     stat_end(kStatFactor, 0.0, (double)tc * tc * tc, s);
     stat_begin(s);
     launch_times_small<T>(n, tc, Cb, Rinv, Hb, s);
@@ -403,7 +425,7 @@ ecg_status ecg_inner(const ecg_operator* Aop, const ecg_partition* P, const ecg_
     launch_small_gram<T>(n, tc, Hb, Yb, r, small_part, small_out, s);
     stat_end(kStatSmallGram, w * n * (2 * tc + 1), 2.0 * n * tc * (tc + 1), s);
     stat_begin(s);
-    launch_factor(1, tc, tl, small_out, tau, Cinv, beta, st, s);
+    launch_factor(1, tc, tl, small_out, nullptr, tau, Cinv, beta, st, s);
     stat_end(kStatFactor, 0.0, (double)tc * tc * tc, s);
     const long long woff = q.place(tc);  // may drop the oldest blocks (already used above)
     T* Wslot = Qbase + (size_t)woff * n;
@@ -427,7 +449,7 @@ ecg_status ecg_inner(const ecg_operator* Aop, const ecg_partition* P, const ecg_
     q.push(woff, tc);
     res->mem += hst.keep_a;
     // a column dropped once stays zero in A W, so it is counted only where it is lost
-    res->deflated += (from_r ? tl : prev_kept) - hst.keep_a;
+    res->deflated += ((from_r || msdo) ? tl : prev_kept) - hst.keep_a;
     prev_kept = hst.keep_a;
     const double rho = std::sqrt(std::max(hst.rr, 0.0));
     tol1 = std::fabs(rho - rho_prev) / rho0;
@@ -684,6 +706,7 @@ ecg_status ecg_options_default(ecg_options* o) {
   o->max_outer = 20;
   o->deflate_tol = 1e-14;
   o->precond = ECG_PRECOND_NONE;
+  o->variant = ECG_SRE_CG2;
   return ECG_OK;
 }
 

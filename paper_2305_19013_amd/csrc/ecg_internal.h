@@ -100,8 +100,12 @@ void launch_small_gram(int n, int tc, const T* X, const T* Y, const T* r, double
 // mode 1 (A step): in = S followed by u (tc); writes Cinv, beta = Cinv Cinv^T u (tc) and
 //   st->keep_a.
 // tc_live: columns >= tc_live are padding (always dropped, not counted as deflated).
-void launch_factor(int mode, int tc, int tc_live, const double* in, double tau, double* inv,
+// ref (nullable): a tc x tc matrix whose diagonal is the pivot-test reference (mode 0).
+void launch_factor(int mode, int tc, int tc_live, const double* in, const double* ref, double tau, double* inv,
                    double* beta, IterStatus* st, hipStream_t s);
+// MSDO-CG candidate: out = S + P diag(-u) for row-major n x tc blocks (u: tc values).
+template <typename T>
+void launch_msdo_combine(int n, int tc, const T* S, const T* P, const double* u, T* out, hipStream_t s);
 
 // out = X M for row-major n x tc X and a tc x tc matrix M (FP64, converted to T).
 template <typename T>

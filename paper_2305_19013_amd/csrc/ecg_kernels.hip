@@ -576,7 +576,7 @@ k_reduce_small_stage(int len, int nchunks, int per, const double* __restrict__ p
 // The factor R lives in the upper triangle of A (row j = R[j][.]); the strictly upper part
 // of X = R^{-1} is kept transposed in the strictly lower triangle of A and diag(X) in xd.
 __global__ void __launch_bounds__(kBlock)
-k_factor(int mode, int tc, int tc_live, const double* __restrict__ in, double tau,
+k_factor(int mode, int tc, int tc_live, const double* __restrict__ in, const double* __restrict__ ref, double tau,
          double* __restrict__ inv, double* __restrict__ beta, IterStatus* __restrict__ st) {
   __shared__ double A[kMaxT * kMaxT];
   __shared__ double d0[kMaxT];
@@ -590,7 +590,8 @@ k_factor(int mode, int tc, int tc_live, const double* __restrict__ in, double ta
   if (tid == 0) brk = 0;
   __syncthreads();
   if (tid < tc) {
-    d0[tid] = A[tid * kMaxT + tid];
+    // reference of the pivot test: the column's squared norm before CGS2 when given
+    d0[tid] = ref ? ref[tid * tc + tid] : A[tid * kMaxT + tid];
     u[tid] = (mode == 1) ? in[tc * tc + tid] : 0.0;
   }
   __syncthreads();
@@ -1099,10 +1100,30 @@ void launch_small_gram(int n, int tc, const T* X, const T* Y, const T* r, double
   hipLaunchKernelGGL(k_reduce_small, dim3(cdiv(nout, kBlock)), dim3(kBlock), 0, s, nout, nch, part, out);
 }
 
-void launch_factor(int mode, int tc, int tc_live, const double* in, double tau, double* inv, double* beta,
-                   IterStatus* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_factor, dim3(1), dim3(kBlock), 0, s, mode, tc, tc_live, in, tau, inv, beta, st);
+void launch_factor(int mode, int tc, int tc_live, const double* in, const double* ref, double tau, double* inv,
+                   double* beta, IterStatus* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_factor, dim3(1), dim3(kBlock), 0, s, mode, tc, tc_live, in, ref, tau, inv, beta, st);
 }
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_msdo_combine(long long len, int tc, const T* __restrict__ S, const T* __restrict__ P, const double* __restrict__ u,
+               T* __restrict__ out) {
+  const long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= len) return;
+  const int c = (int)(e % tc);
+  out[e] = S[e] - P[e] * (T)u[c];  // beta = -u
+}
+
+template <typename T>
+void launch_msdo_combine(int n, int tc, const T* S, const T* P, const double* u, T* out, hipStream_t s) {
+  const long long len = (long long)n * tc;
+  stat_begin(s);
+  hipLaunchKernelGGL((k_msdo_combine<T>), dim3(cdiv(len, kBlock)), dim3(kBlock), 0, s, len, tc, S, P, u, out);
+  stat_end(kStatSplit, 3.0 * sizeof(T) * len, 2.0 * len, s);
+}
+template void launch_msdo_combine<double>(int, int, const double*, const double*, const double*, double*, hipStream_t);
+template void launch_msdo_combine<float>(int, int, const float*, const float*, const double*, float*, hipStream_t);
 
 template <typename T>
 void launch_times_small(int n, int tc, const T* X, const double* M, T* out, hipStream_t s) {

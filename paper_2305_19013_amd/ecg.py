@@ -27,6 +27,7 @@ STATUS_NAMES = {0: "ok", 1: "not_converged", -1: "einval", -2: "enomem", -3: "eh
 REDUCE_NONE, REDUCE_ONCE, REDUCE_REPEAT, REDUCE_SCHEDULE = 0, 1, 2, 3
 FP64, FP32_REFINED = 0, 1
 PRECOND_NONE, PRECOND_SPLIT = 0, 1
+SRE_CG2, MSDO_CG, MODIFIED_MSDO = 0, 1, 2
 
 EXPORTED = (
     "ecg_options_default", "ecg_operator_create_csr", "ecg_operator_destroy", "ecg_operator_info",
@@ -58,6 +59,7 @@ class Options(C.Structure):
         ("deflate_tol", C.c_double),
         ("precond", C.c_int32),
         ("M", C.c_void_p),
+        ("variant", C.c_int32),
     ]
 
 

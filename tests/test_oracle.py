@@ -216,6 +216,18 @@ def test_breakdown_without_deflation():
     assert res.status == "breakdown"
 
 
+def test_noise_columns_deflated_past_exact_termination():
+    # after n/t iterations the Krylov space is the whole space; the next candidate, once
+    # A-orthonormalised against it, is rounding noise relative to its norm beforehand, so
+    # every column is dropped (breakdown) and exactly n A-orthonormal vectors were stored
+    for n, t in [(48, 4), (60, 6)]:
+        A, b, part = tiny(n=n, t=t, seed=17)
+        res = ecg.flexible_sre_cg2(A, b, part, t, tol=1e-30, kmax=n // t + 4, record=True)
+        assert res.status == "breakdown" and res.it == n // t and res.mem == n
+        x = np.linalg.solve(A, b)
+        assert np.linalg.norm(res.x - x) <= 1e-10 * np.linalg.norm(x)
+
+
 def test_kmax_gives_not_converged():
     # the loop guard is k < k_max (Algorithm 3), so at most k_max - 1 iterations
     A, b, part = tiny(n=48, t=4, kappa=1e3, seed=31)
