@@ -35,10 +35,20 @@ Readings where the paper is silent (stated again in the design notes):
   "breakdown");
 * repeated halving (rule REPEAT) and forced switch iterations (SCHEDULE)
   generalise the paper's single switch.
+* restarts (Section 3): a restart at iteration k empties Q and takes the candidate
+  [T(r_{k-1})] at the current width, as at k = 1.  RESTART_EVERY restarts when
+  k mod j == 1; RESTART_TOL restarts when tol1 < restartTol (the statistic of the
+  switch, tested at the same point), at most max_restarts times (0 = no limit);
+  restart_at_switch empties Q at every halving as well (the restarted flexible
+  variants of the memory tables of Section 5.2).  A halving takes precedence over a
+  restart in the same iteration.
 
 Bookkeeping: ``it`` = completed iterations, ``switch_iters`` = iterations at
 which a halved block was formed, ``mem`` = total stored columns (for one
-switch this equals t*sIt + (t/2)*(It - sIt) with sIt = switch_iter - 1).
+switch this equals t*sIt + (t/2)*(It - sIt) with sIt = switch_iter - 1),
+``restart_iters`` = iterations at which Q was emptied, ``mem_cycle`` = the largest
+number of columns stored within one restart cycle (the mem of the restarted runs in
+the Section 5.2 tables; equal to ``mem`` without restarts).
 """
 
 from __future__ import annotations
@@ -52,6 +62,10 @@ REDUCE_NONE = 0
 REDUCE_ONCE = 1
 REDUCE_REPEAT = 2
 REDUCE_SCHEDULE = 3
+
+RESTART_NONE = 0
+RESTART_EVERY = 1
+RESTART_TOL = 2
 
 
 def split(v: np.ndarray, part: np.ndarray, t: int) -> np.ndarray:
@@ -206,10 +220,24 @@ class EcgResult:
     iterates: list = field(default_factory=list)
     blocks: list = field(default_factory=list)
     residuals: list = field(default_factory=list)
+    restart_iters: list = field(default_factory=list)
 
     @property
     def mem(self) -> int:
         return int(sum(self.widths))
+
+    @property
+    def mem_cycle(self) -> int:
+        """Largest sum of widths over the iterations of one restart cycle (a cycle starts
+        at iteration 1 and at every restart iteration)."""
+        best = cur = 0
+        starts = set(self.restart_iters)
+        for k, w in enumerate(self.widths, start=1):
+            if k in starts:
+                cur = 0
+            cur += w
+            best = max(best, cur)
+        return int(best)
 
     @property
     def sit(self) -> int:
@@ -237,10 +265,21 @@ def _switch_now(rule, k, tol1, switch_tol, t_cur, t_min, switches, min_gap, sche
     raise ValueError(rule)
 
 
+def _restart_now(rule, k, tol1, every, restart_tol, restarts, max_restarts):
+    if rule == RESTART_NONE:
+        return False
+    if rule == RESTART_EVERY:
+        return (k - 1) % every == 0  # k mod j == 1 (Section 3)
+    if rule == RESTART_TOL:
+        return tol1 < restart_tol and (max_restarts <= 0 or len(restarts) < max_restarts)
+    raise ValueError(rule)
+
+
 def flexible_sre_cg2(A, b, part, t, *, x0=None, tol=1e-8, kmax=20000, reduce=REDUCE_NONE,
                      switch_tol=1e-5, t_min=1, min_gap=1, schedule=(), trunc=0,
                      deflate_tol=1e-14, precond: SplitPreconditioner | None = None,
-                     record=False, candidate="sre") -> EcgResult:
+                     record=False, candidate="sre", restart=RESTART_NONE, restart_every=0,
+                     restart_tol=1e-5, max_restarts=0, restart_at_switch=False) -> EcgResult:
     """Flexibly SRE-CG2 (Algorithm 3); with reduce=REDUCE_NONE it is SRE-CG2
     (Algorithm 1), with trunc>0 the truncated SRE-CG2 of Section 3.
 
@@ -248,6 +287,8 @@ def flexible_sre_cg2(A, b, part, t, *, x0=None, tol=1e-8, kmax=20000, reduce=RED
     part: int array, subdomain of each unknown, values in [0, t).
     candidate: "sre" (W_k = A W_{k-1}) or "modified-msdo" (W_k = [T^t(r_{k-1})],
       the modified MSDO-CG of Section 2.2).
+    restart, restart_every, restart_tol, max_restarts, restart_at_switch: the restarted
+      variants of Section 3 (see the module notes).
     """
     b = np.asarray(b, dtype=np.float64)
     part = np.asarray(part)
@@ -285,6 +326,13 @@ def flexible_sre_cg2(A, b, part, t, *, x0=None, tol=1e-8, kmax=20000, reduce=RED
             level += 1
             t_cur //= 2
             res.switch_iters.append(k)
+            cand = from_residual(r, level, t_cur)
+            if restart_at_switch:
+                res.restart_iters.append(k)
+                blocks, colstart, ncols = [], [], 0
+        elif _restart_now(restart, k, tol1, restart_every, restart_tol, res.restart_iters, max_restarts):
+            res.restart_iters.append(k)
+            blocks, colstart, ncols = [], [], 0  # Q is emptied (Section 3)
             cand = from_residual(r, level, t_cur)
         elif candidate == "modified-msdo":
             cand = from_residual(r, level, t_cur)
@@ -368,7 +416,9 @@ def memory_formula(t: int, it: int, sit: int) -> int:
 
 def flexible_msdo_cg(A, b, part, t, *, x0=None, tol=1e-8, kmax=20000, reduce=REDUCE_NONE, switch_tol=1e-5,
                      t_min=1, min_gap=1, schedule=(), trunc=0, deflate_tol=1e-14,
-                     precond: SplitPreconditioner | None = None, record=False) -> EcgResult:
+                     precond: SplitPreconditioner | None = None, record=False, restart=RESTART_NONE,
+                     restart_every=0, restart_tol=1e-5, max_restarts=0,
+                     restart_at_switch=False) -> EcgResult:
     """Flexibly MSDO-CG (Section 4.4, Algorithm 4; Algorithm 2 without a switch; with a
     split preconditioner, Algorithm 5).
 
@@ -379,7 +429,8 @@ def flexible_msdo_cg(A, b, part, t, *, x0=None, tol=1e-8, kmax=20000, reduce=RED
     r_k = r_{k-1} - V_k alpha_k.  Preconditioned (Algorithm 5):
     beta_k = -V_{k-1}^T (M^{-1} r_{k-1}) and the split term is L^{-T}[T(L^{-1} r_{k-1})].
     Blocks keep t columns (a deflated column stays a zero column), so column j of P_{k-1}
-    always pairs with subdomain j.
+    always pairs with subdomain j.  Restarts (Section 3) as in ``flexible_sre_cg2``: Q is
+    emptied and P_k = [T(r_{k-1})] without the beta term.
     """
     b = np.asarray(b, dtype=np.float64)
     part = np.asarray(part)
@@ -409,6 +460,13 @@ def flexible_msdo_cg(A, b, part, t, *, x0=None, tol=1e-8, kmax=20000, reduce=RED
             level += 1
             t_cur //= 2
             res.switch_iters.append(k)
+            cand = split_term(r, level, t_cur)
+            if restart_at_switch:
+                res.restart_iters.append(k)
+                blocks = []
+        elif _restart_now(restart, k, tol1, restart_every, restart_tol, res.restart_iters, max_restarts):
+            res.restart_iters.append(k)
+            blocks = []
             cand = split_term(r, level, t_cur)
         else:
             rr = r if pre is None else pre.minv(r)

@@ -164,6 +164,86 @@ def test_memory_formula_reproduces_paper_tables():
         assert ecg.memory_formula(t, it, sit) == mem, (m, t, tol)
 
 
+def _restart_rows():
+    rows = []
+    with open(os.path.join(GOLDEN, "paper_restart_memory.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            meth, m, t, tol, *v = line.split()
+            rows.append((meth, m, int(t), tol, *map(int, v)))
+    return rows
+
+
+def test_restart_cycle_memory_reproduces_paper_tables():
+    # one restart at the flexible run's switch iteration sIt + 1; the block formed there
+    # opens the second cycle; mem = the larger of the two cycles (Section 5.2 tables)
+    rows = _restart_rows()
+    assert len(rows) == 144
+    for meth, m, t, tol, it_f, sit, mem_f, it_r, mem_r, it_rf, mem_rf in rows:
+        assert ecg.memory_formula(t, it_f, sit) == mem_f, (meth, m, t, tol)
+        same_t = ecg.EcgResult(x=None, it=it_r, switch_iters=[], widths=[t] * it_r, rho=[1.0], status="",
+                               t_final=t, deflated=0, restart_iters=[sit + 1])
+        assert same_t.mem_cycle == mem_r, (meth, m, t, tol)
+        halved = ecg.EcgResult(x=None, it=it_rf, switch_iters=[sit + 1], rho=[1.0], status="",
+                               widths=[t] * sit + [t // 2] * (it_rf - sit), t_final=t // 2, deflated=0,
+                               restart_iters=[sit + 1])
+        assert halved.mem_cycle == mem_rf, (meth, m, t, tol)
+
+
+def test_restart_tol_fires_at_the_switch_iteration():
+    # the restart test uses the switch statistic at the same point (Section 3), so a single
+    # restart at restartTol happens where the flexible run with switchTol = restartTol halves
+    p = W.config("poisson64")
+    A = p.A.to_scipy()
+    flex = ecg.flexible_sre_cg2(A, p.b, p.part, p.t, tol=p.tol, reduce=ecg.REDUCE_ONCE, switch_tol=1e-4)
+    rs = ecg.flexible_sre_cg2(A, p.b, p.part, p.t, tol=p.tol, restart=ecg.RESTART_TOL, restart_tol=1e-4,
+                              max_restarts=1)
+    rf = ecg.flexible_sre_cg2(A, p.b, p.part, p.t, tol=p.tol, reduce=ecg.REDUCE_ONCE, switch_tol=1e-4,
+                              restart_at_switch=True)
+    assert rs.restart_iters == flex.switch_iters == rf.restart_iters == rf.switch_iters
+    sit = flex.sit
+    assert rs.mem_cycle == p.t * max(sit, rs.it - sit)
+    assert rf.mem_cycle == max(p.t * sit, p.t // 2 * (rf.it - sit))
+    assert rs.status == rf.status == "converged"
+    # the iterates up to the restart are those of the unrestarted run
+    assert rs.rho[:sit + 1] == flex.rho[:sit + 1]
+
+
+@pytest.mark.parametrize("variant", ["sre", "msdo"])
+def test_restarted_cycles_are_galerkin_projections_from_the_restart_point(variant):
+    # restarting every j iterations: inside a cycle the iterate is the Galerkin projection
+    # of the solution onto x_s + K_{i,t}(A, r_s) (SRE-CG2), or onto x_s + span{T(r_s), ...}
+    # (MSDO-CG), with x_s the iterate at the restart (50-digit definitions)
+    A, b, part = tiny(n=40, t=4, kappa=30.0, seed=53)
+    j = 3
+    if variant == "sre":
+        res = ecg.flexible_sre_cg2(A, b, part, 4, tol=1e-14, kmax=9, restart=ecg.RESTART_EVERY,
+                                   restart_every=j, record=True)
+    else:
+        res = ecg.flexible_msdo_cg(A, b, part, 4, tol=1e-14, kmax=9, restart=ecg.RESTART_EVERY,
+                                   restart_every=j, record=True)
+    assert res.restart_iters == [4, 7] and res.mem_cycle == 4 * j
+    for start in (0, 3, 6):
+        xs = np.zeros(len(b)) if start == 0 else res.iterates[start - 1]
+        for i in range(1, j + 1):
+            if start + i > res.it:
+                break
+            if variant == "sre":
+                ref = brute.krylov_projection(A, b, part, 4, i, x0=xs)
+            else:
+                ref = brute.msdo_projection(A, b, part, 4, i, x0=xs)[-1]
+            got = res.iterates[start + i - 1]
+            assert np.linalg.norm(got - ref) <= 1e-10 * np.linalg.norm(ref), (start, i)
+
+
+def test_restart_beyond_the_run_changes_nothing():
+    A, b, part = tiny(n=48, t=4, kappa=1e3, seed=57)
+    ref = ecg.flexible_sre_cg2(A, b, part, 4, tol=1e-10)
+    res = ecg.flexible_sre_cg2(A, b, part, 4, tol=1e-10, restart=ecg.RESTART_EVERY, restart_every=ref.it + 1)
+    assert res.restart_iters == [] and res.it == ref.it and np.array_equal(res.x, ref.x)
+
+
 def test_oracle_memory_matches_its_switch_bookkeeping():
     p = W.config("poisson64")
     A = p.A.to_scipy()
