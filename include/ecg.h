@@ -71,6 +71,18 @@ typedef enum {
   ECG_MODIFIED_MSDO = 2    /* next block [T(r_{k-1})] (modified MSDO-CG, Section 2.2) */
 } ecg_variant;
 
+/* Restarted variants (Section 3): a restart at iteration k empties the stored blocks Q and
+ * takes the candidate [T(r_{k-1})] at the current width, as at k = 1 (for MSDO-CG without
+ * the beta term).  The stopping test stays relative to ||r_0||. */
+typedef enum {
+  ECG_RESTART_NONE = 0,
+  ECG_RESTART_EVERY = 1,  /* restart when k mod restart_every == 1 (k > 1) */
+  ECG_RESTART_TOL = 2     /* restart when |rho_k - rho_{k-1}| / rho_c < restart_tol, tested
+                             where the switch is tested, with rho_c the residual norm the
+                             current cycle started from (rho_0 before the first restart);
+                             at most max_restarts times (0 = no limit) */
+} ecg_restart;
+
 typedef enum {
   ECG_PRECOND_NONE = 0,
   ECG_PRECOND_SPLIT = 1  /* split preconditioner M = L L^T given as an ecg_precond
@@ -114,6 +126,12 @@ typedef struct {
   int32_t precond;         /* ecg_precond_kind */
   const ecg_precond* M;    /* used when precond == ECG_PRECOND_SPLIT */
   int32_t variant;         /* ecg_variant */
+  int32_t restart;         /* ecg_restart */
+  int32_t restart_every;   /* RESTART_EVERY: cycle length j (>= 1) */
+  double restart_tol;      /* RESTART_TOL: restartTol */
+  int32_t max_restarts;    /* RESTART_TOL: limit on the number of restarts, 0 = none */
+  int32_t restart_at_switch; /* != 0: every halving also empties Q (restarted flexible
+                              variant); a halving takes precedence over a restart */
 } ecg_options;
 
 typedef struct {
@@ -131,11 +149,17 @@ typedef struct {
   double relres_true;       /* ||b - A x|| / ||b||, recomputed in FP64 at the end */
   double seconds;           /* wall time of the solve, host clock */
   int32_t status;           /* ecg_status of the solve */
+  int32_t n_restart;        /* number of restarts (including those at a halving) */
+  int32_t restart_iters[8]; /* iteration k of the first restarts */
+  int64_t vectors_peak;     /* largest sum of widths stored within one restart cycle (the
+                               mem of the paper's restarted runs; = vectors_stored without
+                               restarts) */
 } ecg_report;
 
 /* Fill *o with defaults: tol 1e-8, kmax 20000, no reduction, switch_tol 1e-5, t_min 1,
  * min_gap 1, FP64, inner_tol 1e-4, max_outer 20, replace_every 0, trunc 0,
- * q_budget_bytes 0, deflate_tol 1e-14, no preconditioner, SRE-CG2. */
+ * q_budget_bytes 0, deflate_tol 1e-14, no preconditioner, SRE-CG2, no restarts
+ * (restart_every 0, restart_tol 1e-5, max_restarts 0, restart_at_switch 0). */
 ecg_status ecg_options_default(ecg_options* o);
 
 /* Sparse SPD matrix A (n x n) in CSR form, copied to the device.

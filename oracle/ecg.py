@@ -37,8 +37,11 @@ Readings where the paper is silent (stated again in the design notes):
   generalise the paper's single switch.
 * restarts (Section 3): a restart at iteration k empties Q and takes the candidate
   [T(r_{k-1})] at the current width, as at k = 1.  RESTART_EVERY restarts when
-  k mod j == 1; RESTART_TOL restarts when tol1 < restartTol (the statistic of the
-  switch, tested at the same point), at most max_restarts times (0 = no limit);
+  k mod j == 1; RESTART_TOL restarts when |rho_k - rho_{k-1}| / rho_c < restartTol,
+  tested where the switch is tested, with rho_c the residual norm the current cycle
+  started from (rho_0 before the first restart: a restarted cycle is a fresh solve from
+  its own initial guess, while the stopping test keeps rho_0), at most max_restarts
+  times (0 = no limit);
   restart_at_switch empties Q at every halving as well (the restarted flexible
   variants of the memory tables of Section 5.2).  A halving takes precedence over a
   restart in the same iteration.
@@ -303,6 +306,7 @@ def flexible_sre_cg2(A, b, part, t, *, x0=None, tol=1e-8, kmax=20000, reduce=RED
     schedule = set(int(s) for s in schedule)
     rho_prev = rho0
     tol1 = 1.0
+    rho_cyc, tol1_cyc = rho0, 1.0  # restart statistic: relative to the cycle's first residual
     k = 1
     level = 0
     t_cur = t
@@ -330,9 +334,11 @@ def flexible_sre_cg2(A, b, part, t, *, x0=None, tol=1e-8, kmax=20000, reduce=RED
             if restart_at_switch:
                 res.restart_iters.append(k)
                 blocks, colstart, ncols = [], [], 0
-        elif _restart_now(restart, k, tol1, restart_every, restart_tol, res.restart_iters, max_restarts):
+                rho_cyc = rho_prev
+        elif _restart_now(restart, k, tol1_cyc, restart_every, restart_tol, res.restart_iters, max_restarts):
             res.restart_iters.append(k)
             blocks, colstart, ncols = [], [], 0  # Q is emptied (Section 3)
+            rho_cyc = rho_prev
             cand = from_residual(r, level, t_cur)
         elif candidate == "modified-msdo":
             cand = from_residual(r, level, t_cur)
@@ -353,6 +359,7 @@ def flexible_sre_cg2(A, b, part, t, *, x0=None, tol=1e-8, kmax=20000, reduce=RED
         r = r - Z @ alpha
         rho = float(np.linalg.norm(r))
         tol1 = abs(rho - rho_prev) / rho0
+        tol1_cyc = abs(rho - rho_prev) / rho_cyc
         rho_prev = rho
         res.rho.append(rho)
         res.widths.append(W.shape[1])
@@ -445,6 +452,7 @@ def flexible_msdo_cg(A, b, part, t, *, x0=None, tol=1e-8, kmax=20000, reduce=RED
     schedule = set(int(s) for s in schedule)
     pre = precond
     rho_prev, tol1, k, level, t_cur = rho0, 1.0, 1, 0, t
+    rho_cyc, tol1_cyc = rho0, 1.0
     blocks = []
     P_prev = V_prev = None
 
@@ -464,9 +472,11 @@ def flexible_msdo_cg(A, b, part, t, *, x0=None, tol=1e-8, kmax=20000, reduce=RED
             if restart_at_switch:
                 res.restart_iters.append(k)
                 blocks = []
-        elif _restart_now(restart, k, tol1, restart_every, restart_tol, res.restart_iters, max_restarts):
+                rho_cyc = rho_prev
+        elif _restart_now(restart, k, tol1_cyc, restart_every, restart_tol, res.restart_iters, max_restarts):
             res.restart_iters.append(k)
             blocks = []
+            rho_cyc = rho_prev
             cand = split_term(r, level, t_cur)
         else:
             rr = r if pre is None else pre.minv(r)
@@ -487,6 +497,7 @@ def flexible_msdo_cg(A, b, part, t, *, x0=None, tol=1e-8, kmax=20000, reduce=RED
         r = r - V @ alpha
         rho = float(np.linalg.norm(r))
         tol1 = abs(rho - rho_prev) / rho0
+        tol1_cyc = abs(rho - rho_prev) / rho_cyc
         rho_prev = rho
         res.rho.append(rho)
         res.widths.append(live)

@@ -147,6 +147,8 @@ ecg_status make_plan(int64_t n, int t, const ecg_options& o, Plan* p) {
     cap = (long long)std::max(1, o.kmax - 1) * tp;
   }
   if (o.trunc > 0) cap = std::min<long long>(cap, (long long)o.trunc * tp);
+  if (o.restart == ECG_RESTART_EVERY && o.q_budget_bytes == 0)  // one cycle at a time
+    cap = std::min<long long>(cap, (long long)o.restart_every * tp);
   if (cap < tp) return fail(ECG_EINVAL, "q_budget_bytes is smaller than one stored block");
   p->cap = cap;
   size_t off = 0;
@@ -199,6 +201,9 @@ ecg_status check_options(const ecg_options* o) {
   if (o->precond != ECG_PRECOND_NONE && o->precond != ECG_PRECOND_SPLIT) return fail(ECG_EINVAL, "unknown precond");
   if (o->precond == ECG_PRECOND_SPLIT && !o->M) return fail(ECG_EINVAL, "precond SPLIT needs M");
   if (o->variant < ECG_SRE_CG2 || o->variant > ECG_MODIFIED_MSDO) return fail(ECG_EINVAL, "unknown variant");
+  if (o->restart < ECG_RESTART_NONE || o->restart > ECG_RESTART_TOL) return fail(ECG_EINVAL, "unknown restart rule");
+  if (o->restart == ECG_RESTART_EVERY && o->restart_every < 1) return fail(ECG_EINVAL, "restart_every must be >= 1");
+  if (o->max_restarts < 0) return fail(ECG_EINVAL, "max_restarts must be >= 0");
   return ECG_OK;
 }
 
@@ -232,6 +237,10 @@ struct QStore {
     blocks.push_back(QBlock{off, w});
     head = off + w;
   }
+  void clear() {  // a restart: every stored block is discarded
+    blocks.clear();
+    head = 0;
+  }
 };
 
 template <typename T>
@@ -261,6 +270,16 @@ int build_spans(const QStore& q, int trunc, T* Qbase, int n, std::vector<Span<T>
     goff += b.width;
   }
   return goff;  // m
+}
+
+bool restart_now(const ecg_options& o, int k, double tol1, const std::vector<int>& restarts) {
+  switch (o.restart) {
+    case ECG_RESTART_EVERY:
+      return (k - 1) % o.restart_every == 0;  // k mod j == 1
+    case ECG_RESTART_TOL:
+      return tol1 < o.restart_tol && (o.max_restarts == 0 || (int)restarts.size() < o.max_restarts);
+  }
+  return false;
 }
 
 bool switch_now(const ecg_options& o, int k, double tol1, int t_live, const std::vector<int>& switches) {
@@ -304,7 +323,9 @@ struct InnerResult {
   int iters = 0;
   int deflated = 0;
   long long mem = 0;
+  long long mem_peak = 0;  // largest sum of widths within one restart cycle
   std::vector<int> switches;
+  std::vector<int> restarts;
   int t_final = 0;
   double rho0 = 0, rho = 0;
   ecg_status status = ECG_OK;
@@ -347,12 +368,14 @@ ecg_status ecg_inner(const ecg_operator* Aop, const ecg_partition* P, const ecg_
   const double tau = (sizeof(T) == 4 && o.deflate_tol >= 0.0) ? std::max(o.deflate_tol, 1e-10) : o.deflate_tol;
 
   double rho_prev = rho0, tol1 = 1.0;
+  double rho_cyc = rho0, tol1_cyc = 1.0;  // restart statistic, relative to the cycle's first residual
   int k = 1, level = 0;
   const auto t_begin = std::chrono::steady_clock::now();
   int tl = P->t;                 // live width
   int tc = pow2_at_least(tl);    // padded width of the kernels
   IterStatus hst;
   int prev_kept = tl;
+  long long cycle_mem = 0;
   std::vector<double> replaced;  // true residual norms at the residual replacements
   const int kmax = std::max(1, std::min(o.kmax, res->kmax_left));
   while (rho_prev > tol * rho0 && k < kmax) {
@@ -365,6 +388,18 @@ ecg_status ecg_inner(const ecg_operator* Aop, const ecg_partition* P, const ecg_
       tl /= 2;
       tc = pow2_at_least(tl);
       res->switches.push_back(k);
+      from_r = true;
+      if (o.restart_at_switch) {
+        q.clear();
+        cycle_mem = 0;
+        rho_cyc = rho_prev;
+        res->restarts.push_back(k);
+      }
+    } else if (restart_now(o, k, tol1_cyc, res->restarts)) {
+      q.clear();  // Q is emptied; the candidate comes from the residual (Section 3)
+      cycle_mem = 0;
+      rho_cyc = rho_prev;
+      res->restarts.push_back(k);
       from_r = true;
     }
     if (o.variant == ECG_MODIFIED_MSDO) from_r = true;
@@ -448,11 +483,14 @@ ecg_status ecg_inner(const ecg_operator* Aop, const ecg_partition* P, const ecg_
     // ---- bookkeeping (block stored in its slot by the update kernel)
     q.push(woff, tc);
     res->mem += hst.keep_a;
+    cycle_mem += hst.keep_a;
+    res->mem_peak = std::max(res->mem_peak, cycle_mem);
     // a column dropped once stays zero in A W, so it is counted only where it is lost
     res->deflated += ((from_r || msdo) ? tl : prev_kept) - hst.keep_a;
     prev_kept = hst.keep_a;
     const double rho = std::sqrt(std::max(hst.rr, 0.0));
     tol1 = std::fabs(rho - rho_prev) / rho0;
+    tol1_cyc = std::fabs(rho - rho_prev) / rho_cyc;
     rho_prev = rho;
     if (rho_hist) rho_hist[k] = rho;
     if (g_progress_every > 0 && k % g_progress_every == 0) {
@@ -707,6 +745,8 @@ ecg_status ecg_options_default(ecg_options* o) {
   o->deflate_tol = 1e-14;
   o->precond = ECG_PRECOND_NONE;
   o->variant = ECG_SRE_CG2;
+  o->restart = ECG_RESTART_NONE;
+  o->restart_tol = 1e-5;
   return ECG_OK;
 }
 
@@ -996,6 +1036,8 @@ ecg_status ecg_solve(const ecg_operator* A, const ecg_partition* P, const double
       tot.deflated += ir.deflated;
       tot.dropped += ir.dropped;
       for (int sw : ir.switches) tot.switches.push_back(sw);
+      for (int rs : ir.restarts) tot.restarts.push_back(rs);
+      tot.mem_peak = std::max(tot.mem_peak, ir.mem_peak);
       tot.t_final = ir.t_final;
       ++outer;
       launch_axpy_d(n, d, x, s);  // x += d in FP64, then the true FP64 residual below
@@ -1031,6 +1073,9 @@ ecg_status ecg_solve(const ecg_operator* A, const ecg_partition* P, const double
   rep->trunc_used = o->trunc > 0 ? o->trunc : 0;
   rep->blocks_dropped = (int32_t)std::min<long long>(tot.dropped, 0x7fffffff);
   rep->vectors_stored = tot.mem;
+  rep->vectors_peak = tot.mem_peak;
+  rep->n_restart = (int)tot.restarts.size();
+  for (int i = 0; i < (int)tot.restarts.size() && i < 8; ++i) rep->restart_iters[i] = tot.restarts[i];
   rep->seconds = std::chrono::duration<double>(t_end - t_start).count();
   rep->status = final;
   if (final == ECG_EBREAKDOWN) return ECG_EBREAKDOWN;

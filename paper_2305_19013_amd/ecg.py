@@ -28,6 +28,7 @@ REDUCE_NONE, REDUCE_ONCE, REDUCE_REPEAT, REDUCE_SCHEDULE = 0, 1, 2, 3
 FP64, FP32_REFINED = 0, 1
 PRECOND_NONE, PRECOND_SPLIT = 0, 1
 SRE_CG2, MSDO_CG, MODIFIED_MSDO = 0, 1, 2
+RESTART_NONE, RESTART_EVERY, RESTART_TOL = 0, 1, 2
 
 EXPORTED = (
     "ecg_options_default", "ecg_operator_create_csr", "ecg_operator_destroy", "ecg_operator_info",
@@ -60,6 +61,11 @@ class Options(C.Structure):
         ("precond", C.c_int32),
         ("M", C.c_void_p),
         ("variant", C.c_int32),
+        ("restart", C.c_int32),
+        ("restart_every", C.c_int32),
+        ("restart_tol", C.c_double),
+        ("max_restarts", C.c_int32),
+        ("restart_at_switch", C.c_int32),
     ]
 
 
@@ -78,6 +84,9 @@ class Report(C.Structure):
         ("relres_true", C.c_double),
         ("seconds", C.c_double),
         ("status", C.c_int32),
+        ("n_restart", C.c_int32),
+        ("restart_iters", C.c_int32 * 8),
+        ("vectors_peak", C.c_int64),
     ]
 
     def as_dict(self) -> dict:
@@ -90,6 +99,9 @@ class Report(C.Structure):
             "trunc_used": self.trunc_used,
             "blocks_dropped": self.blocks_dropped,
             "vectors_stored": int(self.vectors_stored),
+            "vectors_peak": int(self.vectors_peak),
+            "n_restart": self.n_restart,
+            "restart_iters": list(self.restart_iters[: min(self.n_restart, 8)]),
             "relres_recursive": self.relres_recursive,
             "relres_true": self.relres_true,
             "seconds": self.seconds,

@@ -41,14 +41,16 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layout_matches_c(tmp_path):
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "ecg.h"\n'
-                   'int main(){printf("%zu %zu %zu %zu %zu\\n", sizeof(ecg_options), sizeof(ecg_report),'
-                   ' offsetof(ecg_options, M), offsetof(ecg_report, vectors_stored), offsetof(ecg_report, status));'
+                   'int main(){printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(ecg_options), sizeof(ecg_report),'
+                   ' offsetof(ecg_options, M), offsetof(ecg_report, vectors_stored), offsetof(ecg_report, status),'
+                   ' offsetof(ecg_options, restart_tol), offsetof(ecg_report, vectors_peak));'
                    'return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
     assert vals == [C.sizeof(ecg.Options), C.sizeof(ecg.Report), ecg.Options.M.offset,
-                    ecg.Report.vectors_stored.offset, ecg.Report.status.offset]
+                    ecg.Report.vectors_stored.offset, ecg.Report.status.offset, ecg.Options.restart_tol.offset,
+                    ecg.Report.vectors_peak.offset]
 
 
 def test_options_default_values():
