@@ -7,6 +7,10 @@
       L_ij = (a_ij - sum_{k<j} L_ik L_jk) / L_jj   for (i, j) in the pattern, j < i
       L_ii = sqrt(a_ii - sum_{k<i} L_ik^2)
   with the sums running over the common pattern only.
+* Block-Jacobi Cholesky (Section 5.3, eq. (cholprec)): the same diagonal blocks factored
+  exactly, A_i = L_i L_i^T (LAPACK Cholesky of each dense block), so M is the block
+  diagonal of A itself.  The blocks are independent of t (the paper uses 64 or 128 of
+  them for every t; the t subdomains are unions of consecutive blocks).
 * A factorised approximate inverse M^{-1} = G G^T, for which L^{-1} = G^T and
   L^{-T} = G in the split-preconditioned recurrences (Section 4.5, eq. (zsre2)).
 """
@@ -79,6 +83,34 @@ def _tri_solve(T, X, lower):
 def bj_ic0_preconditioner(A, part) -> tuple[SplitPreconditioner, sp.csr_matrix]:
     """Block-Jacobi IC(0) on the subdomains of ``part``: (preconditioner, L)."""
     L = ic0(block_diagonal_part(A, np.asarray(part)))
+    LT = sp.csr_matrix(L.T)
+    pre = SplitPreconditioner(lambda X: _tri_solve(L, X, True), lambda X: _tri_solve(LT, X, False))
+    return pre, L
+
+
+def block_cholesky(A, blocks) -> sp.csr_matrix:
+    """Exact Cholesky factor of every diagonal block of A (blocks[i] = block of row i):
+    the lower-triangular L with L L^T = blockdiag(A), rows in the matrix ordering."""
+    A = sp.csr_matrix(A)
+    blocks = np.asarray(blocks)
+    n = A.shape[0]
+    rows, cols, vals = [], [], []
+    for g in np.unique(blocks):
+        idx = np.flatnonzero(blocks == g)
+        Ag = A[idx][:, idx].toarray()
+        Lg = np.linalg.cholesky(Ag)  # raises LinAlgError unless the block is SPD
+        r, c = np.nonzero(np.tril(Lg))
+        rows.append(idx[r])
+        cols.append(idx[c])
+        vals.append(Lg[r, c])
+    L = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n))
+    L.sort_indices()
+    return L
+
+
+def bj_chol_preconditioner(A, blocks) -> tuple[SplitPreconditioner, sp.csr_matrix]:
+    """Block-Jacobi exact Cholesky on the blocks of ``blocks``: (preconditioner, L)."""
+    L = block_cholesky(A, blocks)
     LT = sp.csr_matrix(L.T)
     pre = SplitPreconditioner(lambda X: _tri_solve(L, X, True), lambda X: _tri_solve(LT, X, False))
     return pre, L

@@ -16,6 +16,12 @@ from oracle import brute, ecg
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
+def spl_solve(A, b):
+    import scipy.sparse.linalg as spl
+
+    return spl.spsolve(A.tocsc(), b)
+
+
 def tiny(n=40, t=4, kappa=50.0, seed=1):
     A = W.random_spd(n, kappa, seed)
     b = W.rhs_uniform(n, seed + 1)
@@ -380,6 +386,59 @@ def test_block_jacobi_commutes_with_split():
     lhs = pre.linvT(ecg.split(pre.linv(r), p.part >> 1, p.t // 2))
     rhs = pre.minv(ecg.split(r, p.part >> 1, p.t // 2))
     assert np.abs(lhs - rhs).max() <= 1e-12 * np.abs(rhs).max()
+
+
+# ---------------------------------------------------------------- block-Jacobi Cholesky, 64 blocks (Section 5.3)
+def _chol64(scale=8):
+    p = W.config("jump2d512", scale=scale)  # 64x64 grid at scale 8
+    blocks = W.box_partition(p.grid, (8, 8))  # 64 blocks; the 4x8 subdomains are pairs of them
+    return p, blocks
+
+
+def test_block_cholesky_reproduces_the_block_diagonal():
+    from oracle import precond
+
+    p, blocks = _chol64()
+    assert np.array_equal(blocks >> 1, p.part)
+    A = p.A.to_scipy()
+    L = precond.block_cholesky(A, blocks)
+    Ab = precond.block_diagonal_part(A, blocks)
+    assert abs(L @ L.T - Ab).max() <= 1e-12 * abs(Ab).max()
+    Lc = L.tocoo()
+    assert np.all(blocks[Lc.row] == blocks[Lc.col]) and np.all(Lc.row >= Lc.col)
+    assert L.diagonal().min() > 0
+    # exact factor: fill inside the band, unlike IC(0)
+    assert L.nnz > precond.ic0(Ab).nnz
+
+
+def test_one_block_cholesky_solves_in_one_iteration():
+    # M = A: the preconditioned operator is the identity and r_hat_0 is the sum of the
+    # columns of T(r_hat_0), so the first Galerkin iterate is exact (SRE-CG2 and MSDO-CG)
+    from oracle import precond
+
+    p = W.config("learn2d256", seed=5, scale=8)
+    A = p.A.to_scipy()
+    pre, _ = precond.bj_chol_preconditioner(A, np.zeros(p.n, dtype=np.int32))
+    xs = spl_solve(A, p.b)
+    for fn in (ecg.flexible_sre_cg2, ecg.flexible_msdo_cg):
+        res = fn(A, p.b, p.part, p.t, tol=1e-10, precond=pre)
+        assert res.it == 1 and res.status == "converged"
+        assert np.linalg.norm(res.x - xs) <= 1e-10 * np.linalg.norm(xs)
+
+
+def test_block_cholesky_commutes_with_split_on_unions_of_blocks():
+    # the t subdomains are unions of the 64 blocks, so L is block diagonal on them too
+    from oracle import precond
+
+    p, blocks = _chol64()
+    A = p.A.to_scipy()
+    pre, _ = precond.bj_chol_preconditioner(A, blocks)
+    r = W.rhs_uniform(p.n, 9)
+    for lvl in (0, 1):
+        part, t = p.part >> lvl, p.t >> lvl
+        lhs = pre.linvT(ecg.split(pre.linv(r), part, t))
+        rhs = pre.minv(ecg.split(r, part, t))
+        assert np.abs(lhs - rhs).max() <= 1e-12 * np.abs(rhs).max()
 
 
 # ---------------------------------------------------------------- learned G G^T (oracle)
