@@ -187,6 +187,24 @@ void ecg_partition_destroy(ecg_partition* P);
 ecg_status ecg_precond_create_bj_ic0(const ecg_operator* A, const ecg_partition* P,
                                      void* hip_stream, ecg_precond** out);
 
+typedef enum {
+  ECG_BJ_IC0 = 0,  /* incomplete Cholesky with zero fill of every block */
+  ECG_BJ_CHOL = 1  /* exact Cholesky of every block (eq. (cholprec)) */
+} ecg_bj_kind;
+
+/* Block-Jacobi preconditioner on nblocks diagonal blocks of A chosen independently of the
+ * ECG partition (Section 5.3: the paper uses 64 or 128 blocks for every t, the t
+ * subdomains being unions of consecutive blocks).  block: int32[n], block[i] in
+ * [0, nblocks), every block non-empty (device or host per on_device).  Couplings between
+ * blocks are dropped; each block keeps the matrix order of its rows.
+ * ECG_BJ_CHOL stores each factor as a band: the band of a block is the largest distance,
+ * in that order, between a row and a column it couples to, and must be <= 128 (else
+ * ECG_EINVAL): grid blocks at most 128 cells wide along the fastest axis.  Factorisation
+ * runs on the device; a non-positive pivot gives ECG_EBREAKDOWN. */
+ecg_status ecg_precond_create_bj(const ecg_operator* A, int32_t nblocks, const int32_t* block,
+                                 int on_device, int32_t kind, void* hip_stream,
+                                 ecg_precond** out);
+
 /* Factorised approximate inverse M^{-1} = G G^T (so L^{-1} = G^T, L^{-T} = G in
  * eq. (zsre2)).  G is lower triangular in CSR (int64 rowptr, int32 colind, double vals,
  * each row sorted with the diagonal last), device or host per on_device.  Every

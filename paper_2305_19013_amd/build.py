@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libecg.so")
-SOURCES = ["ecg_kernels.hip", "ecg_api.hip", "ecg_nn.hip"]
+SOURCES = ["ecg_kernels.hip", "ecg_api.hip", "ecg_nn.hip", "ecg_band.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -46,9 +46,11 @@ struct ecg_partition {
 };
 
 struct ecg_precond {
-  int kind = 0;  // 0: triangular factor L (block-Jacobi IC(0)); 1: G with M^{-1} = G G^T
+  int kind = 0;  // 0: triangular factor L (block-Jacobi IC(0)); 1: G with M^{-1} = G G^T;
+                 // 2: block-Jacobi exact Cholesky in band panel form
   DevTri tri;
   DevCsr G, Gt;  // kind 1
+  DevBand band;  // kind 2
   std::vector<void*> owned;
 };
 
@@ -311,6 +313,8 @@ template <typename T>
 void precond_apply(const ecg_precond* M, int which, int tc, const T* X, T* Y, hipStream_t s) {
   if (M->kind == 0) {
     launch_trisolve<T>(M->tri, which, tc, X, Y, s);
+  } else if (M->kind == 2) {
+    launch_band_solve<T>(M->band, which, tc, X, Y, s);
   } else {
     launch_spmm<T>(which == 0 ? M->Gt : M->G, tc, X, Y, s);
   }
@@ -833,11 +837,11 @@ void ecg_partition_destroy(ecg_partition* P) {
   delete P;
 }
 
-ecg_status ecg_precond_create_bj_ic0(const ecg_operator* A, const ecg_partition* P, void* hip_stream,
-                                     ecg_precond** out) {
-  if (!A || !P || !out) return fail(ECG_EINVAL, "NULL argument");
-  if (A->n != P->n) return fail(ECG_EINVAL, "operator and partition sizes differ");
-  hipStream_t s = (hipStream_t)hip_stream;
+namespace {
+
+// Block-Jacobi IC(0) on the blocks given by group[i] in [0, ngroups).
+ecg_status build_bj_ic0(const ecg_operator* A, const std::vector<int>& group, int ngroups, hipStream_t s,
+                        ecg_precond** out) {
   const int64_t n = A->n;
   // pattern of L: lower triangle of A restricted to each subdomain, diagonal last
   std::vector<int64_t> rp(n + 1, 0);
@@ -847,7 +851,7 @@ ecg_status ecg_precond_create_bj_ic0(const ecg_operator* A, const ecg_partition*
     bool has_diag = false;
     for (int64_t k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k) {
       const int j = A->col[k];
-      if (j > i || P->host[j] != P->host[i]) continue;
+      if (j > i || group[j] != group[i]) continue;
       if (j == i) has_diag = true;
       ci.push_back(j);
       apos.push_back((int)k);
@@ -858,9 +862,8 @@ ecg_status ecg_precond_create_bj_ic0(const ecg_operator* A, const ecg_partition*
   std::vector<double> v(ci.size(), 0.0);
   auto* M = new ecg_precond();
   M->kind = 0;
-  std::vector<int> group(P->host.begin(), P->host.end());
   std::vector<int> permU;
-  ecg_status st = make_tri(n, group, P->t, rp, ci, v, s, M, &permU);
+  ecg_status st = make_tri(n, group, ngroups, rp, ci, v, s, M, &permU);
   int* d_apos = nullptr;
   int* d_fail = nullptr;
   int* d_perm = nullptr;
@@ -888,6 +891,121 @@ ecg_status ecg_precond_create_bj_ic0(const ecg_operator* A, const ecg_partition*
   }
   *out = M;
   return ECG_OK;
+}
+
+// Block-Jacobi exact Cholesky: band storage per block, factorisation and panel
+// preparation on the device.
+ecg_status build_bj_chol(const ecg_operator* A, const std::vector<int>& group, int ngroups, hipStream_t s,
+                         ecg_precond** out) {
+  const int64_t n = A->n;
+  std::vector<int> row_off(ngroups + 1, 0), local(n);
+  for (int64_t i = 0; i < n; ++i) ++row_off[group[i] + 1];
+  for (int g = 0; g < ngroups; ++g) row_off[g + 1] += row_off[g];
+  std::vector<int> rows(n), fillp(row_off.begin(), row_off.end() - 1);
+  for (int64_t i = 0; i < n; ++i) {
+    const int g = group[i];
+    local[i] = fillp[g] - row_off[g];
+    rows[fillp[g]++] = (int)i;
+  }
+  int wraw = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    bool has_diag = false;
+    for (int64_t k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k) {
+      const int j = A->col[k];
+      if (j == i) has_diag = true;
+      if (j < i && group[j] == group[i]) wraw = std::max(wraw, local[i] - local[j]);
+    }
+    if (!has_diag) return fail(ECG_EINVAL, "matrix has a missing diagonal entry");
+  }
+  if (wraw > kBandMax)
+    return fail(ECG_EINVAL, "block band " + std::to_string(wraw) + " exceeds " + std::to_string(kBandMax) +
+                                " (blocks at most 128 cells wide in matrix order)");
+  const int W = std::max(kPanel, (wraw + kPanel - 1) / kPanel * kPanel);
+  const int ld = W + 1;
+  std::vector<long long> ab_off(ngroups + 1, 0), panel_off(ngroups + 1, 0);
+  for (int g = 0; g < ngroups; ++g) {
+    const int ng = row_off[g + 1] - row_off[g];
+    ab_off[g + 1] = ab_off[g] + (long long)ng * ld;
+    panel_off[g + 1] = panel_off[g] + (ng + kPanel - 1) / kPanel;
+  }
+  std::vector<double> ab(ab_off[ngroups], 0.0);
+  for (int64_t i = 0; i < n; ++i) {
+    const int g = group[i];
+    for (int64_t k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k) {
+      const int j = A->col[k];
+      if (j > i || group[j] != g) continue;
+      ab[ab_off[g] + (long long)local[j] * ld + (local[i] - local[j])] = A->val[k];
+    }
+  }
+  auto* M = new ecg_precond();
+  M->kind = 2;
+  DevBand& B = M->band;
+  B.n = (int)n;
+  B.nblocks = ngroups;
+  B.W = W;
+  B.npanels = panel_off[ngroups];
+  ecg_status st = ECG_OK;
+  long long* d_aboff = nullptr;
+  double* d_ab = nullptr;
+  int* d_fail = nullptr;
+  int hfail = 0;
+  if ((st = copy_in(&B.row_off, row_off.data(), row_off.size(), 0, s)) == ECG_OK &&
+      (st = copy_in(&B.rows, rows.data(), rows.size(), 0, s)) == ECG_OK &&
+      (st = copy_in(&B.panel_off, panel_off.data(), panel_off.size(), 0, s)) == ECG_OK &&
+      (st = copy_in(&d_aboff, ab_off.data(), ab_off.size(), 0, s)) == ECG_OK &&
+      (st = copy_in(&d_ab, ab.data(), ab.size(), 0, s)) == ECG_OK) {
+    const size_t pbytes = (size_t)B.npanels * (2ull * kPanel * kPanel + 2ull * kPanel * W) * sizeof(double);
+    if (hipMalloc(&B.panels, pbytes) != hipSuccess || hipMalloc(&d_fail, sizeof(int)) != hipSuccess) {
+      st = fail(ECG_ENOMEM, "hipMalloc failed for the block Cholesky factors");
+    } else {
+      (void)hipMemsetAsync(d_fail, 0, sizeof(int), s);
+      launch_band_chol(B, B.row_off, d_aboff, d_ab, d_fail, s);
+      launch_band_panels(B, d_aboff, d_ab, s);
+      if (hipMemcpyAsync(&hfail, d_fail, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        st = fail(ECG_EHIP, std::string("block Cholesky: ") + hipGetErrorString(hipGetLastError()));
+    }
+  }
+  (void)hipFree(d_aboff);
+  (void)hipFree(d_ab);
+  (void)hipFree(d_fail);
+  if (st == ECG_OK && hfail) st = fail(ECG_EBREAKDOWN, "block Cholesky pivot not positive (block not SPD)");
+  if (st != ECG_OK) {
+    ecg_precond_destroy(M);
+    return st;
+  }
+  *out = M;
+  return ECG_OK;
+}
+
+}  // namespace
+
+ecg_status ecg_precond_create_bj_ic0(const ecg_operator* A, const ecg_partition* P, void* hip_stream,
+                                     ecg_precond** out) {
+  if (!A || !P || !out) return fail(ECG_EINVAL, "NULL argument");
+  if (A->n != P->n) return fail(ECG_EINVAL, "operator and partition sizes differ");
+  std::vector<int> group(P->host.begin(), P->host.end());
+  return build_bj_ic0(A, group, P->t, (hipStream_t)hip_stream, out);
+}
+
+ecg_status ecg_precond_create_bj(const ecg_operator* A, int32_t nblocks, const int32_t* block, int on_device,
+                                 int32_t kind, void* hip_stream, ecg_precond** out) {
+  if (!A || !block || !out) return fail(ECG_EINVAL, "NULL argument");
+  if (nblocks < 1 || nblocks > (1 << 20)) return fail(ECG_EINVAL, "nblocks out of range");
+  if (kind != ECG_BJ_IC0 && kind != ECG_BJ_CHOL) return fail(ECG_EINVAL, "unknown block-Jacobi kind");
+  hipStream_t s = (hipStream_t)hip_stream;
+  std::vector<int32_t> hb;
+  ecg_status st;
+  if ((st = to_host(hb, block, (size_t)A->n, on_device, s)) != ECG_OK) return st;
+  std::vector<int> count(nblocks, 0);
+  for (int32_t b : hb) {
+    if (b < 0 || b >= nblocks) return fail(ECG_EINVAL, "block id out of range");
+    ++count[b];
+  }
+  for (int c : count)
+    if (c == 0) return fail(ECG_EINVAL, "empty block");
+  std::vector<int> group(hb.begin(), hb.end());
+  return kind == ECG_BJ_IC0 ? build_bj_ic0(A, group, nblocks, s, out) : build_bj_chol(A, group, nblocks, s, out);
 }
 
 ecg_status ecg_precond_create_factor(int64_t n, int64_t nnz, const int64_t* rowptr, const int32_t* colind,
@@ -933,6 +1051,10 @@ void ecg_precond_destroy(ecg_precond* M) {
   (void)hipFree(M->tri.lvl_rows_U);
   free_csr(M->G);
   free_csr(M->Gt);
+  (void)hipFree(M->band.row_off);
+  (void)hipFree(M->band.rows);
+  (void)hipFree(M->band.panel_off);
+  (void)hipFree(M->band.panels);
   delete M;
 }
 

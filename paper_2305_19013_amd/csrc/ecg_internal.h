@@ -141,6 +141,25 @@ struct DevTri {
 // Y = L^{-1} X (which = 0) or Y = L^{-T} X (which = 1) for row-major n x tc blocks.
 template <typename T>
 void launch_trisolve(const DevTri& M, int which, int tc, const T* X, T* Y, hipStream_t s);
+
+// Block-Jacobi exact Cholesky in panel form (see ecg_band.hip for the layout).
+constexpr int kPanel = 32;    // rows per panel
+constexpr int kBandMax = 128; // widest band (multiple of kPanel)
+struct DevBand {
+  int n = 0;
+  int nblocks = 0;
+  int W = 0;                      // band, a multiple of kPanel, <= kBandMax
+  long long npanels = 0;
+  int* row_off = nullptr;         // [nblocks+1] offsets into rows
+  int* rows = nullptr;            // global row of every local row, block by block
+  long long* panel_off = nullptr; // [nblocks+1] first panel of each block
+  double* panels = nullptr;       // npanels records of 2 P^2 + 2 P W doubles
+};
+void launch_band_chol(const DevBand& B, const int* row_off, const long long* ab_off, double* ab, int* fail,
+                      hipStream_t s);
+void launch_band_panels(const DevBand& B, const long long* ab_off, const double* ab, hipStream_t s);
+template <typename T>
+void launch_band_solve(const DevBand& B, int which, int tc, const T* X, T* Y, hipStream_t s);
 // IC(0) numeric factorisation into M.L.val (pattern already set), FP64; sets *fail.
 void launch_ic0(const DevCsr& A, DevTri& M, const int* diag_pos_A, int* fail, hipStream_t s);
 // Copy L values into U (transpose) using a precomputed permutation U.val[k] = L.val[perm[k]].

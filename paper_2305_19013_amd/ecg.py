@@ -29,10 +29,11 @@ FP64, FP32_REFINED = 0, 1
 PRECOND_NONE, PRECOND_SPLIT = 0, 1
 SRE_CG2, MSDO_CG, MODIFIED_MSDO = 0, 1, 2
 RESTART_NONE, RESTART_EVERY, RESTART_TOL = 0, 1, 2
+BJ_IC0, BJ_CHOL = 0, 1
 
 EXPORTED = (
     "ecg_options_default", "ecg_operator_create_csr", "ecg_operator_destroy", "ecg_operator_info",
-    "ecg_partition_create", "ecg_partition_destroy", "ecg_precond_create_bj_ic0",
+    "ecg_partition_create", "ecg_partition_destroy", "ecg_precond_create_bj_ic0", "ecg_precond_create_bj",
     "ecg_precond_create_factor", "ecg_precond_destroy", "ecg_workspace_size", "ecg_solve", "ecg_spmv",
     "ecg_last_error", "ecg_debug_spmm", "ecg_debug_split", "ecg_debug_gram", "ecg_debug_update",
     "ecg_debug_precond_apply", "ecg_stats_enable", "ecg_stats_read", "ecg_progress",
@@ -137,6 +138,7 @@ def lib():
             "ecg_partition_create": (i32, [i64, i32, vp, C.c_int, vp, C.POINTER(vp)]),
             "ecg_partition_destroy": (None, [vp]),
             "ecg_precond_create_bj_ic0": (i32, [vp, vp, vp, C.POINTER(vp)]),
+            "ecg_precond_create_bj": (i32, [vp, i32, vp, C.c_int, i32, vp, C.POINTER(vp)]),
             "ecg_precond_create_factor": (i32, [i64, i64, vp, vp, vp, C.c_int, vp, C.POINTER(vp)]),
             "ecg_precond_destroy": (None, [vp]),
             "ecg_workspace_size": (i32, [vp, vp, C.POINTER(Options), C.POINTER(C.c_size_t)]),
@@ -236,6 +238,15 @@ class Precond:
     def bj_ic0(cls, op: Operator, part: Partition):
         h = C.c_void_p()
         check(lib().ecg_precond_create_bj_ic0(op.handle, part.handle, _stream(), C.byref(h)))
+        return cls(h)
+
+    @classmethod
+    def bj(cls, op: Operator, blocks, kind: int = 1):
+        """Block-Jacobi on blocks independent of the partition (kind BJ_IC0 or BJ_CHOL)."""
+        blocks = np.ascontiguousarray(blocks, dtype=np.int32)
+        h = C.c_void_p()
+        check(lib().ecg_precond_create_bj(op.handle, int(blocks.max()) + 1, blocks.ctypes.data, 0, kind, _stream(),
+                                          C.byref(h)))
         return cls(h)
 
     @classmethod

@@ -1,0 +1,143 @@
+"""GPU parity of the block-Jacobi preconditioners on blocks independent of t (Section 5.3:
+64 or 128 diagonal blocks, exact Cholesky or IC(0)) against the FP64 oracle.
+
+The factor application is compared with SciPy triangular solves of the oracle's factor
+(relative 1e-12 of the largest entry); preconditioned solves keep the parity bar of the
+other solver tests (iteration and switch counts exactly, iterates to 1e-9 relative).
+"""
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spl
+
+import workloads as W
+from oracle import ecg as ora
+from oracle import precond as opre
+
+pytestmark = pytest.mark.gpu
+
+BJ_IC0, BJ_CHOL, MSDO = 0, 1, 1
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible GPU")
+    from paper_2305_19013_amd import ecg
+
+    ecg.lib()
+    return torch, torch.device("cuda:0")
+
+
+def _chol_case(scale, boxes):
+    p = W.config("jump2d512", scale=scale)
+    return p, W.box_partition(p.grid, boxes)
+
+
+def _apply_check(torch, dev, M, L, n, t, seed):
+    X = np.random.default_rng(seed).standard_normal((n, t))
+    Xt = torch.from_numpy(X).to(dev)
+    Yt = torch.empty_like(Xt)
+    M.apply(0, t, Xt, Yt)
+    ref = spl.spsolve_triangular(sp.csr_matrix(L), X, lower=True)
+    assert np.abs(Yt.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+    M.apply(1, t, Xt, Yt)
+    ref = spl.spsolve_triangular(sp.csr_matrix(L.T), X, lower=False)
+    assert np.abs(Yt.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("scale,boxes,t", [(8, (8, 8), 32), (8, (8, 16), 8), (4, (4, 4), 1), (4, (2, 4), 64),
+                                           (4, (2, 4), 2)])
+def test_block_cholesky_apply_matches_oracle(torch_dev, scale, boxes, t):
+    """Bands 8..64 (one or two panels of coupling), ragged last panels, 1..64 columns."""
+    torch, dev = torch_dev
+    from paper_2305_19013_amd import ecg
+
+    p, blocks = _chol_case(scale, boxes)
+    A = p.A.to_scipy()
+    L = opre.block_cholesky(A, blocks)
+    M = ecg.Precond.bj(ecg.Operator.from_csr(p.A), blocks, BJ_CHOL)
+    _apply_check(torch, dev, M, L, p.n, t, seed=t)
+
+
+def test_block_ic0_on_fixed_blocks_apply_matches_oracle(torch_dev):
+    torch, dev = torch_dev
+    from paper_2305_19013_amd import ecg
+
+    p, blocks = _chol_case(4, (8, 16))  # 128 blocks of 16 x 8 cells
+    A = p.A.to_scipy()
+    _, L = opre.bj_ic0_preconditioner(A, blocks)
+    M = ecg.Precond.bj(ecg.Operator.from_csr(p.A), blocks, BJ_IC0)
+    _apply_check(torch, dev, M, L, p.n, 16, seed=3)
+
+
+def _solve(torch, dev, p, M, **kw):
+    from paper_2305_19013_amd import ecg
+
+    op = ecg.Operator.from_csr(p.A)
+    P = ecg.Partition(p.part, p.t)
+    bt = torch.from_numpy(np.ascontiguousarray(p.b)).to(dev)
+    xt = torch.zeros_like(bt)
+    rep, rh = ecg.solve(op, P, bt, xt, ecg.options(M=M(ecg, op), **kw), rho_hist=True)
+    torch.cuda.synchronize()
+    return rep, xt.cpu().numpy(), rh
+
+
+@pytest.mark.parametrize("variant", [0, MSDO])
+def test_chol64_preconditioned_flexible_parity(torch_dev, variant):
+    """Chol64 with the t = 32 subdomains (pairs of blocks), one halving at switchTol 1e-5."""
+    torch, dev = torch_dev
+    p, blocks = _chol_case(8, (8, 8))
+    A = p.A.to_scipy()
+    pre, _ = opre.bj_chol_preconditioner(A, blocks)
+    kw = dict(reduce=ora.REDUCE_ONCE, switch_tol=1e-5, t_min=16)
+    fn = ora.flexible_msdo_cg if variant == MSDO else ora.flexible_sre_cg2
+    ref = fn(A, p.b, p.part, p.t, tol=1e-8, precond=pre, **kw)
+    rep, x, rh = _solve(torch, dev, p, lambda ecg, op: ecg.Precond.bj(op, blocks, BJ_CHOL), tol=1e-8,
+                        variant=variant, **kw)
+    assert rep["status"] == "ok"
+    assert rep["iters"] == ref.it and rep["switch_iters"] == ref.switch_iters
+    assert rep["vectors_stored"] == ref.mem and rep["deflated_cols"] == ref.deflated
+    assert np.abs(rh - np.array(ref.rho)).max() <= 1e-9 * ref.rho[0]
+    assert np.linalg.norm(x - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
+
+
+def test_ichol128_preconditioned_parity(torch_dev):
+    torch, dev = torch_dev
+    p, blocks = _chol_case(4, (8, 16))
+    A = p.A.to_scipy()
+    pre, _ = opre.bj_ic0_preconditioner(A, blocks)
+    ref = ora.flexible_sre_cg2(A, p.b, p.part, p.t, tol=1e-8, precond=pre)
+    rep, x, _ = _solve(torch, dev, p, lambda ecg, op: ecg.Precond.bj(op, blocks, BJ_IC0), tol=1e-8)
+    assert rep["iters"] == ref.it
+    assert np.linalg.norm(x - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
+
+
+def test_one_block_cholesky_converges_in_one_iteration(torch_dev):
+    """M = A (one block, band 64): the first Galerkin iterate is the solution."""
+    torch, dev = torch_dev
+    p = W.config("learn2d256", seed=5, scale=4)
+    A = p.A.to_scipy()
+    rep, x, _ = _solve(torch, dev, p, lambda ecg, op: ecg.Precond.bj(op, np.zeros(p.n, np.int32), BJ_CHOL),
+                       tol=1e-10)
+    xs = spl.spsolve(A.tocsc(), p.b)
+    assert rep["iters"] == 1 and rep["status"] == "ok"
+    assert np.linalg.norm(x - xs) <= 1e-10 * np.linalg.norm(xs)
+
+
+def test_block_cholesky_rejects_wide_band_and_indefinite_block(torch_dev):
+    torch, dev = torch_dev
+    from paper_2305_19013_amd import ecg
+
+    q = W.config("aniso3d128", scale=8)  # 16^3: one block has band 256
+    with pytest.raises(ecg.EcgError, match="band"):
+        ecg.Precond.bj(ecg.Operator.from_csr(q.A), np.zeros(q.n, np.int32), BJ_CHOL)
+    p, blocks = _chol_case(8, (8, 8))
+    neg = W.CSR(p.A.n, p.A.rowptr, p.A.colind, -p.A.vals)  # every block negative definite
+    with pytest.raises(ecg.EcgError):
+        ecg.Precond.bj(ecg.Operator.from_csr(neg), blocks, BJ_CHOL)
+    with pytest.raises(ecg.EcgError):
+        ecg.Precond.bj(ecg.Operator.from_csr(p.A), np.full(p.n, 3, np.int32), BJ_CHOL)  # empty blocks 0..2
