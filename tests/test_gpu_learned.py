@@ -168,3 +168,26 @@ def test_training_lowers_loss_and_iterations(env):
     it_j = np.mean([r["iters"] for r in res["jacobi"]])
     assert all(r["status"] == "ok" for r in res["learned"])
     assert it_l < it_j, (it_l, it_j)
+
+
+def test_committed_parameters_gain_on_heldout_operators(env):
+    """The parameters trained on 2000 full-size operators (256x256, t = 16) and stored with
+    the package: on held-out operators ECG with the learned G G^T converges, in fewer
+    iterations than its Jacobi start, and well before unpreconditioned ECG does."""
+    import json
+    import os
+
+    torch, dev, learned = env
+    path = os.path.join(os.path.dirname(learned.__file__), "trained", "learn2d256.json")
+    meta = json.load(open(path))
+    assert len(meta["params"]) == learned.NPARAM
+    p0, _ = learned.family(0)
+    m = learned.LearnedFactor(*p0.grid, np.asarray(meta["params"]), dev)
+    th0 = W.init_params(meta["init_seed"])
+    res = learned.evaluate(m, (2000, 2001, 2002), dev, kinds=("learned", "jacobi"), params_jacobi=th0)
+    it_l = [r["iters"] for r in res["learned"]]
+    it_j = [r["iters"] for r in res["jacobi"]]
+    assert all(r["status"] == "ok" and r["relres_true"] <= 1.01e-8 for r in res["learned"])
+    assert all(a < 0.7 * b for a, b in zip(it_l, it_j)), (it_l, it_j)
+    plain = learned.evaluate(m, (2000,), dev, kinds=("plain",), kmax=2 * max(it_l))
+    assert plain["plain"][0]["status"] == "not_converged"
