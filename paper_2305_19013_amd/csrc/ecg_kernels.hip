@@ -130,22 +130,51 @@ k_gather(int nnz, const double* __restrict__ src, const int* __restrict__ perm, 
 }
 
 // ------------------------------------------------------------------ SpMM
-// Y = A X, row-major n x TC blocks.  TC lanes per row: lane c accumulates column c, so a
-// wavefront reads TC contiguous values of X per nonzero (coalesced block rows).
+// Y = A X, row-major n x TC blocks.  Each lane owns VL consecutive columns of one row
+// (one 16-byte load of X per nonzero), so TC / VL lanes share a row and a wavefront reads
+// whole contiguous block rows of X.  The nonzeros of a row are taken eight at a time: the
+// column indices and values first, then the eight block-row loads of X back to back, so
+// the gathers of a stencil row are all in flight together; a slot past the end of the row
+// re-reads the row's own block row with weight zero (the diagonal is always present).
+// Products are summed in the stored order of the row.
+template <typename T, int TC>
+struct SpmmShape {
+  static constexpr int VL = (16 / (int)sizeof(T)) < TC ? (16 / (int)sizeof(T)) : TC;  // columns per lane
+  static constexpr int LPR = TC / VL;                                                   // lanes per row
+  static constexpr int RPB = kBlock / LPR;                                              // rows per workgroup
+};
+
 template <typename T, int TC>
 __global__ void __launch_bounds__(kBlock)
 k_spmm(int n, int nwg, const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ v,
        const T* __restrict__ X, T* __restrict__ Y) {
-  constexpr int RPB = kBlock / TC;
+  using S = SpmmShape<T, TC>;
+  typedef T Vec __attribute__((ext_vector_type(S::VL)));
+  constexpr int KB = 8;
   const int blk = xcd_block();
   if (blk >= nwg) return;
-  const int row = blk * RPB + (int)threadIdx.x / TC;
-  const int c = (int)threadIdx.x % TC;
+  const int row = blk * S::RPB + (int)threadIdx.x / S::LPR;
+  const int c = ((int)threadIdx.x % S::LPR) * S::VL;
   if (row >= n) return;
-  T acc = T(0);
-  const int k1 = rp[row + 1];
-  for (int k = rp[row]; k < k1; ++k) acc += v[k] * X[(size_t)ci[k] * TC + c];
-  Y[(size_t)row * TC + c] = acc;
+  const T* __restrict__ Xc = X + c;
+  Vec acc = Vec(0);
+  const int k0 = rp[row], k1 = rp[row + 1];
+  for (int kb = k0; kb < k1; kb += KB) {
+    int col[KB];
+    T val[KB];
+#pragma unroll
+    for (int u = 0; u < KB; ++u) {
+      const bool ok = kb + u < k1;
+      col[u] = ok ? ci[kb + u] : row;
+      val[u] = ok ? v[kb + u] : T(0);
+    }
+    Vec xv[KB];
+#pragma unroll
+    for (int u = 0; u < KB; ++u) xv[u] = *reinterpret_cast<const Vec*>(Xc + (size_t)col[u] * TC);
+#pragma unroll
+    for (int u = 0; u < KB; ++u) acc += val[u] * xv[u];
+  }
+  *reinterpret_cast<Vec*>(Y + (size_t)row * TC + c) = acc;
 }
 
 // ------------------------------------------------------------------ split T^t
@@ -747,6 +776,107 @@ k_final_update(int n, int nwg, const T* __restrict__ H, const T* __restrict__ Y,
   if (threadIdx.x == 0) part[blk] = tot;
 }
 
+// ------------------------------------------------------------------ n x t block times t x t (MFMA)
+// Out = X M for a row-major n x TC block X and a TC x TC matrix M (FP64 on input), on
+// matrix cores, TC >= 16.  A wavefront owns RT tiles of 16 rows; K runs over the TC
+// columns of X, 16 at a time: each lane reads four consecutive values of one row with one
+// vector load and instruction s pairs lane group g with column 4g+s (the same
+// permutation of K is applied to the rows of M, staged in LDS).
+// FINAL: the fused update of the block iteration.  The same M (= C^{-1}) multiplies H
+// and Y (W = H C^{-1} into the stored-block slot, Z = Y C^{-1} the next candidate), and
+// one more 16-column tile of the B operand carries beta in its first column, so that the
+// products H beta and Y beta come out of the same instructions: x += H beta,
+// r -= Y beta, and the squared norm of the new r is reduced per workgroup.
+template <int TC>
+struct SmallTile {
+  static constexpr int RT = TC >= 64 ? 1 : (TC == 32 ? 2 : 4);  // row tiles per wavefront
+  static constexpr int ROWS = 4 * 16 * RT;                        // rows per workgroup
+};
+
+template <typename T, typename TX, int TC, bool FINAL>
+__global__ void __launch_bounds__(kBlock)
+k_small_mfma(int n, int nwg, const T* __restrict__ H, const T* __restrict__ Yin, const double* __restrict__ M,
+             const double* __restrict__ beta, T* __restrict__ Wout, T* __restrict__ Zout, TX* __restrict__ x,
+             T* __restrict__ r, double* __restrict__ part) {
+  using V = typename Mfma<T>::V;
+  typedef T T4 __attribute__((ext_vector_type(4)));
+  constexpr int TB = TC / 16;
+  constexpr int NT = FINAL ? TB + 1 : TB;  // output column tiles (FINAL: + the beta tile)
+  constexpr int LD = NT * 16;
+  constexpr int RT = SmallTile<TC>::RT;
+  __shared__ T Ms[TC * LD];
+  __shared__ double red[FINAL ? kBlock : 1];
+  for (int e = threadIdx.x; e < TC * LD; e += kBlock) {
+    const int kk = e / LD, j = e % LD;
+    Ms[e] = (T)(j < TC ? M[kk * TC + j] : ((FINAL && j == TC) ? beta[kk] : 0.0));
+  }
+  __syncthreads();
+  const int blk = xcd_block();
+  if (blk >= nwg) return;  // uniform over the workgroup: no later barrier is split
+  const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+  const int g = lane >> 4, c = lane & 15;
+  const int rowbase = blk * SmallTile<TC>::ROWS + wave * 16 * RT;
+  V aw[RT][NT], az[FINAL ? RT : 1][FINAL ? NT : 1];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      aw[rt][nt] = V{0, 0, 0, 0};
+      if constexpr (FINAL) az[rt][nt] = V{0, 0, 0, 0};
+    }
+#pragma unroll
+  for (int kc = 0; kc < TC / 16; ++kc) {
+    T4 qh[RT], qy[FINAL ? RT : 1];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      const int row = rowbase + rt * 16 + c;
+      const size_t off = (size_t)row * TC + kc * 16 + 4 * g;
+      qh[rt] = row < n ? *reinterpret_cast<const T4*>(H + off) : T4{0, 0, 0, 0};
+      if constexpr (FINAL) qy[rt] = row < n ? *reinterpret_cast<const T4*>(Yin + off) : T4{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const int kk = kc * 16 + 4 * g + s4;
+      T gv[NT];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) gv[nt] = Ms[kk * LD + nt * 16 + c];
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          aw[rt][nt] = Mfma<T>::run(qh[rt][s4], gv[nt], aw[rt][nt]);
+          if constexpr (FINAL) az[rt][nt] = Mfma<T>::run(qy[rt][s4], gv[nt], az[rt][nt]);
+        }
+    }
+  }
+  double rr = 0.0;
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = rowbase + rt * 16 + Mfma<T>::row(g, v);
+      if (row < n) {
+#pragma unroll
+        for (int tb = 0; tb < TB; ++tb) {
+          Wout[(size_t)row * TC + tb * 16 + c] = aw[rt][tb][v];
+          if constexpr (FINAL) Zout[(size_t)row * TC + tb * 16 + c] = az[rt][tb][v];
+        }
+        if constexpr (FINAL) {
+          if (c == 0) {  // column 0 of the beta tile: (H beta)_row and (Y beta)_row
+            x[row] += (TX)aw[rt][TB][v];
+            const T rn = r[row] - az[rt][TB][v];
+            r[row] = rn;
+            rr += (double)rn * (double)rn;
+          }
+        }
+      }
+    }
+  if constexpr (FINAL) {
+    const double tot = block_sum(rr, red);
+    if (threadIdx.x == 0) part[blk] = tot;
+  }
+}
+
 // ------------------------------------------------------------------ triangular solves
 // One workgroup per independent group (subdomain); levels processed in order with a
 // workgroup barrier in between.  which = 0: forward (L, diagonal last in each row);
@@ -898,7 +1028,7 @@ void launch_spmm(const DevCsr& A, int tc, const T* X, T* Y, hipStream_t s) {
   switch (tc) {
 #define C(TC)                                                                                    \
   case TC: {                                                                                     \
-    const int nwg = cdiv(A.n, kBlock / TC);                                                      \
+    const int nwg = cdiv(A.n, SpmmShape<T, TC>::RPB);                                            \
     stat_begin(s);                                                                               \
     hipLaunchKernelGGL((k_spmm<T, TC>), dim3(pad8(nwg)), dim3(kBlock), 0, s, A.n, nwg, A.rowptr, \
                        A.col, vals_of<T>(A), X, Y);                                              \
@@ -1134,7 +1264,16 @@ void launch_times_small(int n, int tc, const T* X, const double* M, T* out, hipS
     hipLaunchKernelGGL((k_times_small<T, TC>), dim3(pad8(nwg)), dim3(kBlock), 0, s, n, nwg, X, M, out); \
     break;                                                                                            \
   }
-    ECG_TC_CASES(C)
+    C(1) C(2) C(4) C(8)
+#undef C
+#define C(TC)                                                                                         \
+  case TC: {                                                                                          \
+    const int nwg = cdiv(n, SmallTile<TC>::ROWS);                                                     \
+    hipLaunchKernelGGL((k_small_mfma<T, double, TC, false>), dim3(pad8(nwg)), dim3(kBlock), 0, s, n, nwg, X, \
+                       nullptr, M, nullptr, out, nullptr, nullptr, nullptr, nullptr);                 \
+    break;                                                                                            \
+  }
+    C(16) C(32) C(64)
 #undef C
   }
 }
@@ -1153,7 +1292,18 @@ int launch_final_update(int n, int tc, const T* H, const T* Y, const double* Cin
     stat_end(kStatFinal, 4.0 * sizeof(T) * n * TC + (double)n * (2 * sizeof(TX) + 2 * sizeof(T)),      \
              4.0 * n * TC * TC + 4.0 * n * TC, s);                                                     \
     break;
-    ECG_TC_CASES(C)
+    C(1) C(2) C(4) C(8)
+#undef C
+#define C(TC)                                                                                          \
+  case TC:                                                                                             \
+    nwg = cdiv(n, SmallTile<TC>::ROWS);                                                                \
+    stat_begin(s);                                                                                     \
+    hipLaunchKernelGGL((k_small_mfma<T, TX, TC, true>), dim3(pad8(nwg)), dim3(kBlock), 0, s, n, nwg, H, Y, \
+                       Cinv, beta, Wq, Zn, x, r, part);                                                \
+    stat_end(kStatFinal, 4.0 * sizeof(T) * n * TC + (double)n * (2 * sizeof(TX) + 2 * sizeof(T)),      \
+             4.0 * n * TC * TC + 4.0 * n * TC, s);                                                     \
+    break;
+    C(16) C(32) C(64)
 #undef C
   }
   return nwg;
