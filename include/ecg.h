@@ -282,6 +282,11 @@ ecg_status ecg_debug_gram(int64_t n, int32_t nb, int32_t wq, const double* Q, in
 /* W -= Q G (same layouts as ecg_debug_gram; W row-major n x t, updated in place). */
 ecg_status ecg_debug_update(int64_t n, int32_t nb, int32_t wq, const double* Q, int32_t t,
                             const double* G, double* W, void* hip_stream);
+/* FP32 forms of the two kernels above (the FP32_REFINED path), same layouts. */
+ecg_status ecg_debug_gram_f32(int64_t n, int32_t nb, int32_t wq, const float* Q, int32_t t,
+                              const float* Y, float* G, void* hip_stream);
+ecg_status ecg_debug_update_f32(int64_t n, int32_t nb, int32_t wq, const float* Q, int32_t t,
+                                const float* G, float* W, void* hip_stream);
 /* Apply the preconditioner factors to a row-major n x t block: which = 0: Y = L^{-1} X,
  * which = 1: Y = L^{-T} X. */
 ecg_status ecg_debug_precond_apply(const ecg_precond* M, int32_t which, int32_t t,

@@ -1229,31 +1229,57 @@ ecg_status ecg_debug_split(const ecg_partition* P, int32_t level, const double* 
 
 static bool pow2_le64(int v) { return v >= 1 && v <= 64 && !(v & (v - 1)); }
 
-ecg_status ecg_debug_gram(int64_t n, int32_t nb, int32_t wq, const double* Q, int32_t t, const double* Y, double* G,
-                          void* hip_stream) {
+}  // extern "C"
+
+namespace {
+template <typename T>
+ecg_status debug_gram_t(int64_t n, int32_t nb, int32_t wq, const T* Q, int32_t t, const T* Y, T* G, void* hip_stream) {
   if (!Q || !Y || !G || n <= 0 || nb < 1 || !pow2_le64(wq) || !pow2_le64(t)) return fail(ECG_EINVAL, "bad argument");
   hipStream_t s = (hipStream_t)hip_stream;
-  Span<double> sp{Q, (long long)n * wq, nb, wq, 0};
+  Span<T> sp{Q, (long long)n * wq, nb, wq, 0};
   const int m = nb * wq;
   const size_t cap = (size_t)1 << 26;
-  double* part = nullptr;
-  HIPCHK(hipMalloc(&part, cap * sizeof(double)));
-  launch_gram<double>((int)n, &sp, 1, m, t, Y, G, part, cap, s);
+  T* part = nullptr;
+  HIPCHK(hipMalloc(&part, cap * sizeof(T)));
+  launch_gram<T>((int)n, &sp, 1, m, t, Y, G, part, cap, s);
   hipError_t e = hipStreamSynchronize(s);
   (void)hipFree(part);
   if (e != hipSuccess) return fail(ECG_EHIP, hipGetErrorString(e));
   return ECG_OK;
 }
 
-ecg_status ecg_debug_update(int64_t n, int32_t nb, int32_t wq, const double* Q, int32_t t, const double* G, double* W,
-                            void* hip_stream) {
+template <typename T>
+ecg_status debug_update_t(int64_t n, int32_t nb, int32_t wq, const T* Q, int32_t t, const T* G, T* W, void* hip_stream) {
   if (!Q || !W || !G || n <= 0 || nb < 1 || !pow2_le64(wq) || !pow2_le64(t)) return fail(ECG_EINVAL, "bad argument");
   hipStream_t s = (hipStream_t)hip_stream;
-  Span<double> sp{Q, (long long)n * wq, nb, wq, 0};
-  launch_update<double>((int)n, &sp, 1, t, G, W, s);
+  Span<T> sp{Q, (long long)n * wq, nb, wq, 0};
+  launch_update<T>((int)n, &sp, 1, t, G, W, s);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
   return ECG_OK;
+}
+}  // namespace
+
+extern "C" {
+
+ecg_status ecg_debug_gram(int64_t n, int32_t nb, int32_t wq, const double* Q, int32_t t, const double* Y, double* G,
+                          void* hip_stream) {
+  return debug_gram_t<double>(n, nb, wq, Q, t, Y, G, hip_stream);
+}
+
+ecg_status ecg_debug_update(int64_t n, int32_t nb, int32_t wq, const double* Q, int32_t t, const double* G, double* W,
+                            void* hip_stream) {
+  return debug_update_t<double>(n, nb, wq, Q, t, G, W, hip_stream);
+}
+
+ecg_status ecg_debug_gram_f32(int64_t n, int32_t nb, int32_t wq, const float* Q, int32_t t, const float* Y, float* G,
+                              void* hip_stream) {
+  return debug_gram_t<float>(n, nb, wq, Q, t, Y, G, hip_stream);
+}
+
+ecg_status ecg_debug_update_f32(int64_t n, int32_t nb, int32_t wq, const float* Q, int32_t t, const float* G, float* W,
+                                void* hip_stream) {
+  return debug_update_t<float>(n, nb, wq, Q, t, G, W, hip_stream);
 }
 
 ecg_status ecg_debug_precond_apply(const ecg_precond* M, int32_t which, int32_t t, const double* X, double* Y,

@@ -293,11 +293,19 @@ struct Mfma<float> {
   __device__ __forceinline__ static int row(int g, int v) { return 4 * g + v; }
 };
 
-// Q columns handled by one Gram wavefront (more columns = fewer re-reads of Y).
+// Q columns handled by one Gram wavefront (more columns = fewer re-reads of Y).  A lane
+// reads TA >= 16/sizeof(T) consecutive values of a row (at least one 16-byte load); when a
+// stored block is narrower than 16*TA columns, BPG consecutive blocks form one "virtual
+// block" of 16*TA columns, lane c reading block (TA*c)/WQ of the group.
 template <typename T, int WQ, int TC>
 struct GramTile {
   static constexpr int QC = (TC >= 64 || sizeof(T) == 8) ? 64 : 128;
-  static constexpr int JB = QC >= WQ ? QC / WQ : 1;
+  static constexpr int VPL = 16 / (int)sizeof(T);            // values per 16-byte load
+  static constexpr int TA = (WQ / 16 > VPL) ? WQ / 16 : VPL;  // values per lane per row
+  static constexpr int VW = 16 * TA;                          // virtual block width
+  static constexpr int BPG = VW / WQ;                         // stored blocks per virtual block
+  static constexpr int JB = QC >= VW ? QC / VW : 1;           // virtual blocks per wavefront
+  static constexpr int NB = JB * BPG;                         // stored blocks per wavefront
 };
 
 // CGS2 Gram on matrix cores: one wavefront = JB stored blocks x one chunk of rows.
@@ -311,8 +319,9 @@ __global__ void __launch_bounds__(64)
 k_gram_mfma(int n, Span<T> sp, int rows_per_chunk, int units, int nwork, const T* __restrict__ Y,
             T* __restrict__ part, int m) {
   using V = typename Mfma<T>::V;
-  constexpr int JB = GramTile<T, WQ, TC>::JB;
-  constexpr int TA = WQ / 16, TB = TC / 16;
+  using GT = GramTile<T, WQ, TC>;
+  constexpr int JB = GT::JB, BPG = GT::BPG;
+  constexpr int TA = GT::TA, TB = TC / 16;
   typedef T TAv __attribute__((ext_vector_type(TA)));
   typedef T TBv __attribute__((ext_vector_type(TB)));
   constexpr int RQ = 4;  // row quads loaded ahead
@@ -323,7 +332,7 @@ k_gram_mfma(int n, Span<T> sp, int rows_per_chunk, int units, int nwork, const T
   const int w = xcd_block();
   if (w >= nwork) return;
   const int chunk = w / units;
-  const int j0 = (w % units) * JB;
+  const int j0 = (w % units) * GT::NB;
   const int r0 = chunk * rows_per_chunk;
   const int r1 = min(n, r0 + rows_per_chunk);
   V acc[JB][TA][TB];
@@ -337,8 +346,9 @@ k_gram_mfma(int n, Span<T> sp, int rows_per_chunk, int units, int nwork, const T
   bool jv[JB];
 #pragma unroll
   for (int jb = 0; jb < JB; ++jb) {
-    jv[jb] = (j0 + jb) < sp.nblk;
-    Qb[jb] = sp.base + (size_t)(jv[jb] ? j0 + jb : j0) * sp.stride + TA * c;
+    const int blk = j0 + jb * BPG + (TA * c) / WQ;  // stored block this lane reads
+    jv[jb] = blk < sp.nblk;
+    Qb[jb] = sp.base + (size_t)(jv[jb] ? blk : j0) * sp.stride + (TA * c) % WQ;
   }
   const T* __restrict__ Yc = Y + TB * c;
   // operands of 4*RQ rows, double-buffered: the next batch is requested before the
@@ -379,13 +389,14 @@ k_gram_mfma(int n, Span<T> sp, int rows_per_chunk, int units, int nwork, const T
   if (row < r1) product(qa0, yb0);
 #pragma unroll
   for (int jb = 0; jb < JB; ++jb) {
-    if (!jv[jb]) continue;
-    const size_t rowbase = (size_t)chunk * m + sp.goff + (size_t)(j0 + jb) * WQ;
+    const size_t rowbase = (size_t)chunk * m + sp.goff + (size_t)(j0 + jb * BPG) * WQ;
 #pragma unroll
     for (int ta = 0; ta < TA; ++ta)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const size_t a = rowbase + TA * Mfma<T>::row(g, v) + ta;
+        const int vc = TA * Mfma<T>::row(g, v) + ta;  // column of the virtual block
+        if (j0 + jb * BPG + vc / WQ >= sp.nblk) continue;
+        const size_t a = rowbase + vc;
 #pragma unroll
         for (int tb = 0; tb < TB; ++tb) part[a * TC + TB * c + tb] = acc[jb][ta][tb][v];
       }
@@ -1100,8 +1111,8 @@ template <typename T, int WQ, int TC>
 static void gram_span(int n, const Span<T>& sp, int rpc, int nch, const T* Y, T* part, int m, hipStream_t s) {
   stat_begin(s);
   if constexpr (WQ >= 16 && TC >= 16) {
-    constexpr int JB = GramTile<T, WQ, TC>::JB;
-    const int units = (sp.nblk + JB - 1) / JB;
+    constexpr int NB = GramTile<T, WQ, TC>::NB;
+    const int units = (sp.nblk + NB - 1) / NB;
     const int nwork = units * nch;
     hipLaunchKernelGGL((k_gram_mfma<T, WQ, TC>), dim3(pad8(nwork)), dim3(64), 0, s, n, sp, rpc, units, nwork, Y,
                        part, m);

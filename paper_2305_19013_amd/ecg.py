@@ -35,7 +35,7 @@ EXPORTED = (
     "ecg_options_default", "ecg_operator_create_csr", "ecg_operator_destroy", "ecg_operator_info",
     "ecg_partition_create", "ecg_partition_destroy", "ecg_precond_create_bj_ic0", "ecg_precond_create_bj",
     "ecg_precond_create_factor", "ecg_precond_destroy", "ecg_workspace_size", "ecg_solve", "ecg_spmv",
-    "ecg_last_error", "ecg_debug_spmm", "ecg_debug_split", "ecg_debug_gram", "ecg_debug_update",
+    "ecg_last_error", "ecg_debug_spmm", "ecg_debug_split", "ecg_debug_gram", "ecg_debug_update", "ecg_debug_gram_f32", "ecg_debug_update_f32",
     "ecg_debug_precond_apply", "ecg_stats_enable", "ecg_stats_read", "ecg_progress",
 )
 STAT_NAMES = ("spmm", "cgs2_gram", "cgs2_gram_reduce", "cgs2_update", "small_gram", "factor",
@@ -149,6 +149,8 @@ def lib():
             "ecg_debug_split": (i32, [vp, i32, dp, dp, vp]),
             "ecg_debug_gram": (i32, [i64, i32, i32, dp, i32, dp, dp, vp]),
             "ecg_debug_update": (i32, [i64, i32, i32, dp, i32, dp, dp, vp]),
+            "ecg_debug_gram_f32": (i32, [i64, i32, i32, dp, i32, dp, dp, vp]),
+            "ecg_debug_update_f32": (i32, [i64, i32, i32, dp, i32, dp, dp, vp]),
             "ecg_debug_precond_apply": (i32, [vp, i32, i32, dp, dp, vp]),
             "ecg_stats_enable": (i32, [C.c_int]),
             "ecg_progress": (i32, [i32]),
@@ -342,11 +344,15 @@ def debug_split(part: Partition, level: int, v, out):
 
 
 def debug_gram(n, nb, wq, Q, t, Y, G):
-    check(lib().ecg_debug_gram(n, nb, wq, _ptr(Q), t, _ptr(Y), _ptr(G), _stream()))
+    """G = Q^T Y; FP64 or FP32 tensors (all of one type)."""
+    fn = lib().ecg_debug_gram_f32 if str(Q.dtype) == "torch.float32" else lib().ecg_debug_gram
+    check(fn(n, nb, wq, _ptr(Q), t, _ptr(Y), _ptr(G), _stream()))
 
 
 def debug_update(n, nb, wq, Q, t, G, W):
-    check(lib().ecg_debug_update(n, nb, wq, _ptr(Q), t, _ptr(G), _ptr(W), _stream()))
+    """W -= Q G; FP64 or FP32 tensors (all of one type)."""
+    fn = lib().ecg_debug_update_f32 if str(Q.dtype) == "torch.float32" else lib().ecg_debug_update
+    check(fn(n, nb, wq, _ptr(Q), t, _ptr(G), _ptr(W), _stream()))
 
 
 def stats_enable(on: bool = True):

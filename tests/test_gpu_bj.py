@@ -1,9 +1,13 @@
 """GPU parity of the block-Jacobi preconditioners on blocks independent of t (Section 5.3:
 64 or 128 diagonal blocks, exact Cholesky or IC(0)) against the FP64 oracle.
 
-The factor application is compared with SciPy triangular solves of the oracle's factor
-(relative 1e-12 of the largest entry); preconditioned solves keep the parity bar of the
-other solver tests (iteration and switch counts exactly, iterates to 1e-9 relative).
+The factor application is compared with SciPy triangular solves of the oracle's factor.
+Two exact Cholesky factors of one block computed in different orders (LAPACK's blocked
+order in the oracle, a right-looking band sweep on the device) agree only to about
+kappa(A_g) u in their action, so that comparison allows 8 u max_g kappa(A_g) relative to the
+largest entry (never less than 1e-13); IC(0), computed in the same order on both sides, is
+held to 1e-12.  Preconditioned solves keep the parity bar of the other solver tests
+(iteration and switch counts exactly, iterates to 1e-9 relative).
 """
 
 import numpy as np
@@ -37,16 +41,25 @@ def _chol_case(scale, boxes):
     return p, W.box_partition(p.grid, boxes)
 
 
-def _apply_check(torch, dev, M, L, n, t, seed):
+def _apply_check(torch, dev, M, L, n, t, seed, rel=1e-12):
     X = np.random.default_rng(seed).standard_normal((n, t))
     Xt = torch.from_numpy(X).to(dev)
     Yt = torch.empty_like(Xt)
     M.apply(0, t, Xt, Yt)
     ref = spl.spsolve_triangular(sp.csr_matrix(L), X, lower=True)
-    assert np.abs(Yt.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+    err = np.abs(Yt.cpu().numpy() - ref).max() / np.abs(ref).max()
+    assert err <= rel, (err, rel)
     M.apply(1, t, Xt, Yt)
     ref = spl.spsolve_triangular(sp.csr_matrix(L.T), X, lower=False)
-    assert np.abs(Yt.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+    err = np.abs(Yt.cpu().numpy() - ref).max() / np.abs(ref).max()
+    assert err <= rel, (err, rel)
+
+
+def _kappa_bound(A, blocks):
+    """8 u max_g kappa_2(A_g) over the diagonal blocks (dense SVD), at least 1e-13."""
+    kap = max(np.linalg.cond(A[idx][:, idx].toarray()) for idx in (np.flatnonzero(blocks == g)
+                                                                    for g in np.unique(blocks)))
+    return max(1e-13, 8 * 2.0 ** -53 * kap)
 
 
 @pytest.mark.parametrize("scale,boxes,t", [(8, (8, 8), 32), (8, (8, 16), 8), (4, (4, 4), 1), (4, (2, 4), 64),
@@ -60,7 +73,22 @@ def test_block_cholesky_apply_matches_oracle(torch_dev, scale, boxes, t):
     A = p.A.to_scipy()
     L = opre.block_cholesky(A, blocks)
     M = ecg.Precond.bj(ecg.Operator.from_csr(p.A), blocks, BJ_CHOL)
-    _apply_check(torch, dev, M, L, p.n, t, seed=t)
+    _apply_check(torch, dev, M, L, p.n, t, seed=t, rel=_kappa_bound(A, blocks))
+
+
+@pytest.mark.parametrize("t", [1, 16])
+def test_block_cholesky_apply_well_conditioned_band64(torch_dev, t):
+    """Constant coefficients (kappa < 1e3), band 48 (stored as 64: two coupling panels): the
+    two factorisation orders agree to 1e-12."""
+    torch, dev = torch_dev
+    from paper_2305_19013_amd import ecg
+
+    csr = W.fd_operator((40, 48), (1.0, 1.0))  # 48 cells wide, 40 tall
+    A = csr.to_scipy()
+    blocks = (np.arange(csr.n) // 48 >= 17).astype(np.int32)  # 816 and 1104 rows: ragged last panels
+    L = opre.block_cholesky(A, blocks)
+    M = ecg.Precond.bj(ecg.Operator.from_csr(csr), blocks, BJ_CHOL)
+    _apply_check(torch, dev, M, L, csr.n, t, seed=5, rel=1e-12)
 
 
 def test_block_ic0_on_fixed_blocks_apply_matches_oracle(torch_dev):

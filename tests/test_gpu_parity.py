@@ -78,30 +78,41 @@ def test_split_is_exact(torch_dev, level):
     assert np.array_equal(out.cpu().numpy(), ora.split(v, ora.merged_partition(p.part, level), tl))
 
 
-@pytest.mark.parametrize("n,nb,wq,t", [(4099, 3, 8, 8), (4099, 2, 32, 16), (70001, 5, 32, 32),
-                                       (3000, 1, 64, 64), (1027, 4, 16, 64), (5000, 3, 64, 8)])
-def test_gram_and_update_match_numpy(torch_dev, n, nb, wq, t):
+GRAM_CASES = [(4099, 3, 8, 8), (4099, 2, 32, 16), (70001, 5, 32, 32), (3000, 1, 64, 64), (1027, 4, 16, 64),
+              (5000, 3, 64, 8), (1027, 3, 16, 32), (4099, 5, 16, 16), (2053, 7, 32, 32), (777, 1, 16, 16)]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("n,nb,wq,t", GRAM_CASES)
+def test_gram_and_update_match_numpy(torch_dev, n, nb, wq, t, dtype):
+    """Blocks narrower than a 16-byte lane load are read in groups (FP64 width 16, FP32
+    widths 16 and 32), including groups cut short by the end of the span.  Bounds: the
+    standard dot-product error bound, gamma_K sum |a||b| with unit roundoff u of the type."""
     torch, dev = torch_dev
     from paper_2305_19013_amd import ecg
 
+    u = 2.0 ** -53 if dtype == "f64" else 2.0 ** -24
+    npt = np.float64 if dtype == "f64" else np.float32
+    tt = torch.float64 if dtype == "f64" else torch.float32
     rng = np.random.default_rng(n + t)
-    Q = rng.standard_normal((nb, n, wq))
-    Y = rng.standard_normal((n, t))
-    Qm = np.concatenate([Q[j] for j in range(nb)], axis=1)  # n x (nb*wq)
-    Qt = _t(torch, dev, Q)
-    Yt = _t(torch, dev, Y)
-    Gt = torch.empty((nb * wq, t), dtype=torch.float64, device=dev)
+    Q = rng.standard_normal((nb, n, wq)).astype(npt)
+    Y = rng.standard_normal((n, t)).astype(npt)
+    Qm = np.concatenate([Q[j] for j in range(nb)], axis=1).astype(np.float64)  # n x (nb*wq)
+    Qt = torch.from_numpy(Q).to(dev)
+    Yt = torch.from_numpy(Y).to(dev)
+    Gt = torch.empty((nb * wq, t), dtype=tt, device=dev)
     ecg.debug_gram(n, nb, wq, Qt, t, Yt, Gt)
-    G = Gt.cpu().numpy()
-    ref = Qm.T @ Y
-    bound = 1e-15 * np.sqrt(n) * 10 * (np.abs(Qm).T @ np.abs(Y))
+    G = Gt.cpu().numpy().astype(np.float64)
+    ref = Qm.T @ Y.astype(np.float64)
+    bound = 2 * n * u * (np.abs(Qm).T @ np.abs(Y.astype(np.float64))) + 1e-30
     assert np.all(np.abs(G - ref) <= bound)
-    W0 = rng.standard_normal((n, t))
-    Wt = _t(torch, dev, W0)
+    W0 = rng.standard_normal((n, t)).astype(npt)
+    Wt = torch.from_numpy(W0).to(dev)
     ecg.debug_update(n, nb, wq, Qt, t, Gt, Wt)
-    refw = W0 - Qm @ G
-    boundw = 1e-15 * nb * wq * 4 * (np.abs(W0) + np.abs(Qm) @ np.abs(G))
-    assert np.all(np.abs(Wt.cpu().numpy() - refw) <= boundw)
+    Gq = Gt.cpu().numpy().astype(np.float64)
+    refw = W0.astype(np.float64) - Qm @ Gq
+    boundw = 2 * (nb * wq + 1) * u * (np.abs(W0.astype(np.float64)) + np.abs(Qm) @ np.abs(Gq)) + 1e-30
+    assert np.all(np.abs(Wt.cpu().numpy().astype(np.float64) - refw) <= boundw)
 
 
 def test_block_jacobi_ic0_apply_matches_oracle(torch_dev):
