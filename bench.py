@@ -10,7 +10,9 @@ b ~ U(-1, 1).  Inputs are resident in HBM before the timed region starts.
 The 2D jumping-coefficient workload jump2d512 is not the timed step: without a
 preconditioner its stored basis outgrows HBM long before 1e-8 (4000 iterations,
 235 GB of stored blocks, residual still 0.45).  It is reported beside the step with the
-block-Jacobi IC(0) preconditioner on its 32 subdomains (Section 5.3 of the paper).
+block-Jacobi preconditioners of Section 5.3 of the paper: IC(0) on its 32 subdomains, and
+the exact Cholesky of 64 blocks of 64 x 64 cells (the paper's best) with flexibly
+SRE-CG2 and flexibly MSDO-CG.
 
 Reported:
   value          seconds per FP64 solve of aniso3d128 (higher_is_better false)
@@ -19,6 +21,8 @@ Reported:
   roofline       the kernel class with the most time in the FP64 step: algorithmic bytes
                  per launch / HIP-event launch time, against 8 TB/s HBM
   jump2d512_bj   jump2d512 with block-Jacobi IC(0), FP64 and FP32-refined
+  jump2d512_chol64  jump2d512 with block-Jacobi Cholesky on 64 blocks, FP64, flexibly
+                 SRE-CG2 and flexibly MSDO-CG
   learn2d256_learned  ECG with the trained G G^T vs its Jacobi start, block-Jacobi IC(0) and
                  no preconditioner on held-out 256x256 jumping-coefficient operators
   cpu_baseline   the FP64 oracle on the host (bounded sample, extrapolated; see 'sample')
