@@ -576,8 +576,41 @@ ecg_status check_csr(int64_t n, int64_t nnz, const std::vector<int64_t>& rp, con
 }
 
 // Upload a host CSR (int64 rowptr) as DevCsr with an FP32 copy of the values.
+// Diagonal form for the products (SpMM): kept when the matrix has at most kMaxDiag distinct
+// diagonals and they are at least 70% filled, as for stencil operators on grids.
+ecg_status upload_dia(int64_t n, const std::vector<int64_t>& rp, const std::vector<int32_t>& ci,
+                      const std::vector<double>& v, hipStream_t s, DevCsr* out) {
+  std::vector<int> offs;
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+      const long long o = (long long)ci[k] - i;
+      if (std::find(offs.begin(), offs.end(), (int)o) == offs.end()) {
+        offs.push_back((int)o);
+        if ((int)offs.size() > kMaxDiag) return ECG_OK;  // not a few-diagonal matrix
+      }
+    }
+  }
+  if (offs.empty() || (double)v.size() < 0.7 * (double)offs.size() * (double)n) return ECG_OK;
+  std::sort(offs.begin(), offs.end());
+  const int nd = (int)offs.size();
+  std::vector<double> dv((size_t)nd * n, 0.0);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+      const int d = (int)(std::lower_bound(offs.begin(), offs.end(), (int)(ci[k] - i)) - offs.begin());
+      dv[(size_t)d * n + i] += v[k];  // duplicates, if any, add up as in the CSR product
+    }
+  ecg_status st;
+  if ((st = copy_in(&out->dval, dv.data(), dv.size(), 0, s)) != ECG_OK) return st;
+  HIPCHK(hipMalloc(&out->dvalf, dv.size() * sizeof(float)));
+  launch_cast_val((int)dv.size(), out->dval, out->dvalf, s);
+  out->ndiag = nd;
+  for (int d = 0; d < kMaxDiag; ++d) out->dia.off[d] = d < nd ? offs[d] : 0;
+  return ECG_OK;
+}
+
 ecg_status upload_csr(int64_t n, const std::vector<int64_t>& rp, const std::vector<int32_t>& ci,
-                      const std::vector<double>& v, hipStream_t s, DevCsr* out, std::vector<void*>* owned) {
+                      const std::vector<double>& v, hipStream_t s, DevCsr* out, std::vector<void*>* owned,
+                      bool with_dia = false) {
   std::vector<int> rp32(n + 1);
   for (int64_t i = 0; i <= n; ++i) rp32[i] = (int)rp[i];
   const size_t nnz = v.size();
@@ -589,6 +622,8 @@ ecg_status upload_csr(int64_t n, const std::vector<int64_t>& rp, const std::vect
   if ((st = copy_in(&out->val, v.data(), nnz, 0, s)) != ECG_OK) return st;
   HIPCHK(hipMalloc(&out->valf, std::max<size_t>(nnz, 1) * sizeof(float)));
   if (nnz) launch_cast_val((int)nnz, out->val, out->valf, s);
+  if (with_dia && (size_t)n * kMaxDiag < ((size_t)1 << 31) && (st = upload_dia(n, rp, ci, v, s, out)) != ECG_OK)
+    return st;
   HIPCHK(hipStreamSynchronize(s));
   if (owned) {
     owned->push_back(out->rowptr);
@@ -604,6 +639,8 @@ void free_csr(DevCsr& A) {
   (void)hipFree(A.col);
   (void)hipFree(A.val);
   (void)hipFree(A.valf);
+  (void)hipFree(A.dval);
+  (void)hipFree(A.dvalf);
   A = DevCsr();
 }
 
@@ -766,7 +803,7 @@ ecg_status ecg_operator_create_csr(int64_t n, int64_t nnz, const int64_t* rowptr
       (st = to_host(op->col, colind, (size_t)nnz, on_device, s)) != ECG_OK ||
       (st = to_host(op->val, vals, (size_t)nnz, on_device, s)) != ECG_OK ||
       (st = check_csr(n, nnz, op->rowptr, op->col)) != ECG_OK ||
-      (st = upload_csr(n, op->rowptr, op->col, op->val, s, &op->A, nullptr)) != ECG_OK) {
+      (st = upload_csr(n, op->rowptr, op->col, op->val, s, &op->A, nullptr, true)) != ECG_OK) {
     free_csr(op->A);
     delete op;
     return st;
@@ -1032,8 +1069,8 @@ ecg_status ecg_precond_create_factor(int64_t n, int64_t nnz, const int64_t* rowp
   for (size_t k = 0; k < vt.size(); ++k) vt[k] = v[perm[k]];
   auto* M = new ecg_precond();
   M->kind = 1;
-  if ((st = upload_csr(n, rp, ci, v, s, &M->G, nullptr)) != ECG_OK ||
-      (st = upload_csr(n, rpt, cit, vt, s, &M->Gt, nullptr)) != ECG_OK) {
+  if ((st = upload_csr(n, rp, ci, v, s, &M->G, nullptr, true)) != ECG_OK ||
+      (st = upload_csr(n, rpt, cit, vt, s, &M->Gt, nullptr, true)) != ECG_OK) {
     ecg_precond_destroy(M);
     return st;
   }

@@ -14,6 +14,10 @@ constexpr int kMaxT = 64;        // widest block (t x t factor runs in one workg
 constexpr int kSmallChunks = 1024;  // partial sums of the t x t Grams
 
 // Device copy of a sparse matrix in CSR form (int32 row pointers).
+constexpr int kMaxDiag = 16;  // diagonal (DIA) form kept for matrices with at most this many
+struct DiaOffsets {
+  int off[kMaxDiag];  // distinct column - row offsets, ascending
+};
 struct DevCsr {
   int n = 0;
   int nnz = 0;
@@ -21,6 +25,12 @@ struct DevCsr {
   int* col = nullptr;
   double* val = nullptr;
   float* valf = nullptr;  // FP32 copy of val
+  // diagonal form of the same matrix (ndiag = 0 when not kept): dval[d*n + i] = a(i, i+off[d]),
+  // 0 where that entry is absent or outside the matrix
+  int ndiag = 0;
+  DiaOffsets dia{};
+  double* dval = nullptr;
+  float* dvalf = nullptr;
 };
 
 // One contiguous run of stored blocks of equal width: block j of the span starts at

@@ -177,6 +177,38 @@ k_spmm(int n, int nwg, const int* __restrict__ rp, const int* __restrict__ ci, c
   *reinterpret_cast<Vec*>(Y + (size_t)row * TC + c) = acc;
 }
 
+// The same product for a matrix kept in diagonal form: no index loads, the ND block-row
+// gathers of a row issued together, the diagonal values read coalesced along the rows.
+// Diagonals are summed in ascending offset order, the column order of the CSR rows, and an
+// absent entry contributes 0 * x, so the result equals the CSR kernel's.
+template <typename T, int TC, int MAXD>
+__global__ void __launch_bounds__(kBlock)
+k_spmm_dia(int n, int nwg, int nd, DiaOffsets dia, const T* __restrict__ dv, const T* __restrict__ X,
+           T* __restrict__ Y) {
+  using S = SpmmShape<T, TC>;
+  typedef T Vec __attribute__((ext_vector_type(S::VL)));
+  const int blk = xcd_block();
+  if (blk >= nwg) return;
+  const int row = blk * S::RPB + (int)threadIdx.x / S::LPR;
+  const int c = ((int)threadIdx.x % S::LPR) * S::VL;
+  if (row >= n) return;
+  const T* __restrict__ Xc = X + c;
+  T val[MAXD];
+  Vec xv[MAXD];
+#pragma unroll
+  for (int d = 0; d < MAXD; ++d) {
+    const int j = row + dia.off[d];
+    const bool ok = d < nd && j >= 0 && j < n;
+    val[d] = ok ? dv[(size_t)d * n + row] : T(0);
+    xv[d] = ok ? *reinterpret_cast<const Vec*>(Xc + (size_t)j * TC) : Vec(0);
+  }
+  Vec acc = Vec(0);
+#pragma unroll
+  for (int d = 0; d < MAXD; ++d)
+    if (d < nd) acc += val[d] * xv[d];
+  *reinterpret_cast<Vec*>(Y + (size_t)row * TC + c) = acc;
+}
+
 // ------------------------------------------------------------------ split T^t
 template <typename T, typename TV, int TC>
 __global__ void __launch_bounds__(kBlock)
@@ -1033,6 +1065,12 @@ template <>
 const double* vals_of<double>(const DevCsr& A) { return A.val; }
 template <>
 const float* vals_of<float>(const DevCsr& A) { return A.valf; }
+template <typename T>
+static const T* dia_vals_of(const DevCsr& A);
+template <>
+const double* dia_vals_of<double>(const DevCsr& A) { return A.dval; }
+template <>
+const float* dia_vals_of<float>(const DevCsr& A) { return A.dvalf; }
 
 template <typename T>
 void launch_spmm(const DevCsr& A, int tc, const T* X, T* Y, hipStream_t s) {
@@ -1041,9 +1079,18 @@ void launch_spmm(const DevCsr& A, int tc, const T* X, T* Y, hipStream_t s) {
   case TC: {                                                                                     \
     const int nwg = cdiv(A.n, SpmmShape<T, TC>::RPB);                                            \
     stat_begin(s);                                                                               \
-    hipLaunchKernelGGL((k_spmm<T, TC>), dim3(pad8(nwg)), dim3(kBlock), 0, s, A.n, nwg, A.rowptr, \
-                       A.col, vals_of<T>(A), X, Y);                                              \
-    stat_end(kStatSpmm, (double)A.nnz * (sizeof(T) + 4) + 4.0 * (A.n + 1) + 2.0 * sizeof(T) * A.n * TC, \
+    if (A.ndiag > 0 && A.ndiag <= 8)                                                             \
+      hipLaunchKernelGGL((k_spmm_dia<T, TC, 8>), dim3(pad8(nwg)), dim3(kBlock), 0, s, A.n, nwg, A.ndiag, \
+                         A.dia, dia_vals_of<T>(A), X, Y);                                        \
+    else if (A.ndiag > 8)                                                                        \
+      hipLaunchKernelGGL((k_spmm_dia<T, TC, kMaxDiag>), dim3(pad8(nwg)), dim3(kBlock), 0, s, A.n, nwg, \
+                         A.ndiag, A.dia, dia_vals_of<T>(A), X, Y);                               \
+    else                                                                                         \
+      hipLaunchKernelGGL((k_spmm<T, TC>), dim3(pad8(nwg)), dim3(kBlock), 0, s, A.n, nwg, A.rowptr, \
+                         A.col, vals_of<T>(A), X, Y);                                            \
+    stat_end(kStatSpmm, (A.ndiag > 0 ? (double)A.ndiag * A.n * sizeof(T)                        \
+                                     : (double)A.nnz * (sizeof(T) + 4) + 4.0 * (A.n + 1)) +     \
+                            2.0 * sizeof(T) * A.n * TC,                                          \
              2.0 * A.nnz * TC, s);                                                               \
     break;                                                                                       \
   }
