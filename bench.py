@@ -22,7 +22,9 @@ Reported:
                  per launch / HIP-event launch time, against 8 TB/s HBM
   jump2d512_bj   jump2d512 with block-Jacobi IC(0), FP64 and FP32-refined
   jump2d512_chol64  jump2d512 with block-Jacobi Cholesky on 64 blocks, FP64, flexibly
-                 SRE-CG2 and flexibly MSDO-CG
+                 SRE-CG2 and flexibly MSDO-CG, and the restarted variants of SRE-CG2 (one
+                 restart at restartTol 1e-5; restart at the halving): iterations, stored
+                 vectors and the largest restart cycle
   learn2d256_learned  ECG with the trained G G^T vs its Jacobi start, block-Jacobi IC(0) and
                  no preconditioner on held-out 256x256 jumping-coefficient operators
   cpu_baseline   the FP64 oracle on the host (bounded sample, extrapolated; see 'sample')
@@ -58,12 +60,13 @@ def solve_once(ecg, op, P, b, x, opts, ws):
     return rep
 
 
-def run_form(args, torch, ecg, prob, op, P, b, form, M=None, steps=None, warmup=None, tag="", variant=0):
+def run_form(args, torch, ecg, prob, op, P, b, form, M=None, steps=None, warmup=None, tag="", **extra):
     dev = b.device
     steps = args.steps if steps is None else steps
     warmup = args.warmup if warmup is None else warmup
     common = dict(tol=prob.tol, kmax=args.kmax, reduce=prob.reduce, switch_tol=prob.switch_tol,
-                  t_min=prob.t_min, M=M, variant=variant)
+                  t_min=prob.t_min, M=M)
+    common.update(extra)
     if form == "fp64":
         kw = dict(common, precision=ecg.FP64)
         w = 8
@@ -345,12 +348,19 @@ def main():
         setup = time.perf_counter() - t0
         chol = {"workload": "jump2d512", "precond": "block-Jacobi Cholesky, 64 blocks", "n": pj.n, "t": pj.t,
                 "setup_seconds": round(setup, 4)}
-        for name, variant in (("sre_cg2", ecg.SRE_CG2), ("msdo_cg", ecg.MSDO_CG)):
+        # the memory-bounded alternatives of Section 3 beside the switch rule: one restart at
+        # restartTol = 1e-5 with the same t, and the flexible run that also restarts at its halving
+        runs = (("sre_cg2", dict(variant=ecg.SRE_CG2)), ("msdo_cg", dict(variant=ecg.MSDO_CG)),
+                ("sre_cg2_restarted", dict(reduce=ecg.REDUCE_NONE, restart=ecg.RESTART_TOL, restart_tol=1e-5,
+                                           max_restarts=1)),
+                ("sre_cg2_restarted_flexible", dict(restart_at_switch=1)))
+        for name, extra in runs:
             Rj = run_form(args, torch, ecg, pj, opj, Pj, bj, "fp64", M=Mc, steps=3, warmup=1,
-                          tag=f"jump2d512-chol64-{name} ", variant=variant)
+                          tag=f"jump2d512-chol64-{name} ", **extra)
             rj = Rj["report"]
             chol[name] = {"seconds": round(Rj["seconds"], 4), "iters": rj["iters"],
-                          "switch_iters": rj["switch_iters"], "vectors_stored": rj["vectors_stored"],
+                          "switch_iters": rj["switch_iters"], "restart_iters": rj["restart_iters"],
+                          "vectors_stored": rj["vectors_stored"], "vectors_peak": rj["vectors_peak"],
                           "relres_true": rj["relres_true"], "status": rj["status"]}
         out["jump2d512_chol64"] = chol
     if not args.no_side and not args.no_learned:

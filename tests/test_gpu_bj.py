@@ -169,3 +169,18 @@ def test_block_cholesky_rejects_wide_band_and_indefinite_block(torch_dev):
         ecg.Precond.bj(ecg.Operator.from_csr(neg), blocks, BJ_CHOL)
     with pytest.raises(ecg.EcgError):
         ecg.Precond.bj(ecg.Operator.from_csr(p.A), np.full(p.n, 3, np.int32), BJ_CHOL)  # empty blocks 0..2
+
+
+@pytest.mark.parametrize("variant", [0, MSDO])
+def test_fp32_refined_with_chol64_reaches_fp64_accuracy(torch_dev, variant):
+    """The FP32 form (FP32 blocks, FP64 t x t steps, FP64 residual replacement and outer
+    refinement) under the Chol64 preconditioner, SRE-CG2 and MSDO-CG: the host-recomputed
+    FP64 true residual reaches 1e-8."""
+    torch, dev = torch_dev
+    p, blocks = _chol_case(8, (8, 8))
+    A = p.A.to_scipy()
+    rep, x, _ = _solve(torch, dev, p, lambda ecg, op: ecg.Precond.bj(op, blocks, BJ_CHOL), tol=1e-8,
+                       variant=variant, precision=1, inner_tol=1e-4, replace_every=25, reduce=ora.REDUCE_ONCE,
+                       switch_tol=1e-5, t_min=16)
+    assert rep["status"] == "ok"
+    assert ora.true_relres(A, p.b, x) <= 1.01e-8

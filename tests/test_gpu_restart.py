@@ -109,3 +109,14 @@ def test_restart_options_rejected(torch_dev, poisson):
         _solve(torch, dev, p, restart=ora.RESTART_EVERY, restart_every=0)
     with pytest.raises(ecg.EcgError):
         _solve(torch, dev, p, restart=5)
+
+
+def test_fp32_refined_with_restarts_reaches_fp64_accuracy(torch_dev, poisson):
+    """Restarts inside the FP32 form's inner solves (iteration numbers are those of the inner
+    solve): the refined solution reaches the FP64 true residual 1e-8."""
+    torch, dev = torch_dev
+    p, A = poisson
+    rep, x, _ = _solve(torch, dev, p, tol=1e-8, precision=1, inner_tol=1e-4, replace_every=25,
+                       restart=ora.RESTART_TOL, restart_tol=1e-3)
+    assert rep["status"] == "ok" and rep["n_restart"] >= 1
+    assert ora.true_relres(A, p.b, x) <= 1.01e-8
