@@ -138,7 +138,8 @@ typedef struct {
   int32_t iters;            /* completed block iterations (all inner iterations summed
                                for FP32_REFINED) */
   int32_t n_switch;         /* number of halvings */
-  int32_t switch_iters[8];  /* iteration k at which each halved block was formed */
+  int32_t switch_iters[8];  /* iteration k at which each halved block was formed (FP32_REFINED:
+                               numbered within the refinement step's inner solve) */
   int32_t t_final;          /* block width at the end */
   int32_t outer_iters;      /* refinement steps (1 for FP64) */
   int32_t deflated_cols;    /* columns dropped by deflation */
@@ -150,7 +151,7 @@ typedef struct {
   double seconds;           /* wall time of the solve, host clock */
   int32_t status;           /* ecg_status of the solve */
   int32_t n_restart;        /* number of restarts (including those at a halving) */
-  int32_t restart_iters[8]; /* iteration k of the first restarts */
+  int32_t restart_iters[8]; /* iteration k of the first restarts (numbered like switch_iters) */
   int64_t vectors_peak;     /* largest sum of widths stored within one restart cycle (the
                                mem of the paper's restarted runs; = vectors_stored without
                                restarts) */

@@ -74,6 +74,49 @@ def test_first_iterations_full_size_match_oracle(torch_dev, aniso):
     assert np.abs(rh - np.array(ref.rho)).max() <= 1e-10 * ref.rho[0]
 
 
+@pytest.mark.parametrize("t,its", [(16, 2), (64, 1)])
+def test_aniso_other_widths_full_size_match_oracle(torch_dev, t, its):
+    """aniso3d128 with t = 16 and t = 64 (2x2x4 and 2x2x16 boxes) at full size: the first
+    iterations (two at t = 16 including a CGS2 sweep, one at t = 64)."""
+    torch, dev = torch_dev
+    from paper_2305_19013_amd import ecg
+
+    p = W.config("aniso3d128", t=t)
+    A = p.A.to_scipy()
+    ref = ora.flexible_sre_cg2(A, p.b, p.part, p.t, tol=p.tol, kmax=its + 1)
+    op = ecg.Operator.from_csr(p.A)
+    P = ecg.Partition(p.part, p.t)
+    bt = torch.from_numpy(p.b).to(dev)
+    xt = torch.zeros_like(bt)
+    rep, _ = ecg.solve(op, P, bt, xt, ecg.options(tol=p.tol, kmax=its + 1, q_budget_bytes=3 * p.t * p.n * 8))
+    assert rep["iters"] == ref.it == its
+    x = xt.cpu().numpy()
+    assert np.linalg.norm(x - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
+
+
+def test_jump3d160_full_size_with_halving_matches_oracle(torch_dev):
+    """jump3d160 at full size (n = 4,096,000, t = 64 from 4x4x4 boxes): two iterations, the
+    width halved to 32 at the second (scheduled), on the merged boxes."""
+    torch, dev = torch_dev
+    from paper_2305_19013_amd import ecg
+
+    p = W.config("jump3d160")
+    A = p.A.to_scipy()
+    kw = dict(reduce=ora.REDUCE_SCHEDULE, schedule=[2], t_min=8)
+    ref = ora.flexible_sre_cg2(A, p.b, p.part, p.t, tol=p.tol, kmax=3, **kw)
+    op = ecg.Operator.from_csr(p.A)
+    P = ecg.Partition(p.part, p.t)
+    bt = torch.from_numpy(p.b).to(dev)
+    xt = torch.zeros_like(bt)
+    rep, rh = ecg.solve(op, P, bt, xt, ecg.options(tol=p.tol, kmax=3, q_budget_bytes=3 * p.t * p.n * 8, **kw),
+                        rho_hist=True)
+    assert rep["iters"] == ref.it == 2 and rep["switch_iters"] == [2] and rep["t_final"] == 32
+    assert rep["vectors_stored"] == ref.mem
+    x = xt.cpu().numpy()
+    assert np.linalg.norm(x - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
+    assert np.abs(rh - np.array(ref.rho)).max() <= 1e-10 * ref.rho[0]
+
+
 @pytest.mark.parametrize("kind", ["bj_ic0", "chol64"])
 def test_jump2d512_full_size_solves_to_tolerance(torch_dev, kind):
     """The metric's own 512^2 jumping-coefficient configuration (t = 32, one halving at
