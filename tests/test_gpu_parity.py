@@ -339,3 +339,34 @@ def test_determinism_bitwise(torch_dev):
     r1, x1, _ = _solve(torch, dev, p.A, p.b, p.part, p.t, kmax=40)
     r2, x2, _ = _solve(torch, dev, p.A, p.b, p.part, p.t, kmax=40)
     assert np.array_equal(x1, x2)
+
+
+def test_zero_residual_returns_immediately(torch_dev):
+    """b = 0 with x0 = 0: rho_0 = 0, no iteration, x stays zero (both precision forms)."""
+    torch, dev = torch_dev
+    p = W.config("poisson64")
+    for precision in (0, 1):
+        rep, x, _ = _solve(torch, dev, p.A, np.zeros(p.n), p.part, p.t, tol=p.tol, precision=precision)
+        assert rep["status"] == "ok" and rep["iters"] == 0 and not np.any(x)
+
+
+def test_invalid_inputs_rejected_before_device_work(torch_dev):
+    """Partition values out of range, an empty subdomain, t > 64, NaN in b: ECG_EINVAL."""
+    torch, dev = torch_dev
+    from paper_2305_19013_amd import ecg
+
+    p = W.config("poisson64")
+    bad = p.part.copy()
+    bad[0] = p.t  # out of range
+    with pytest.raises(ecg.EcgError):
+        ecg.Partition(bad, p.t)
+    empty = p.part.copy()
+    empty[empty == 3] = 2  # subdomain 3 empty
+    with pytest.raises(ecg.EcgError):
+        ecg.Partition(empty, p.t)
+    with pytest.raises(ecg.EcgError):
+        ecg.Partition(np.arange(p.n, dtype=np.int32) % 65, 65)
+    b = p.b.copy()
+    b[5] = np.nan
+    with pytest.raises(ecg.EcgError):
+        _solve(torch, dev, p.A, b, p.part, p.t, tol=p.tol)
