@@ -133,3 +133,19 @@ def test_variant_rejected(torch_dev):
     p = W.config("poisson64")
     with pytest.raises(ecg.EcgError):
         _solve(torch, dev, p.A, p.b, p.part, p.t, variant=7)
+
+
+def test_truncated_msdo_and_modified_msdo_parity(torch_dev):
+    """Truncation (Section 3) applies to MSDO-CG and modified MSDO-CG as to SRE-CG2: Q is the
+    last trunc blocks."""
+    torch, dev = torch_dev
+    p = W.config("poisson64")
+    A = p.A.to_scipy()
+    ref = ora.flexible_msdo_cg(A, p.b, p.part, p.t, tol=p.tol, trunc=6)
+    rep, x, rh = _solve(torch, dev, p.A, p.b, p.part, p.t, tol=p.tol, variant=MSDO, trunc=6)
+    assert rep["iters"] == ref.it and rep["trunc_used"] == 6
+    assert np.linalg.norm(x - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
+    ref = ora.flexible_sre_cg2(A, p.b, p.part, p.t, tol=p.tol, trunc=2, candidate="modified-msdo")
+    rep, x, rh = _solve(torch, dev, p.A, p.b, p.part, p.t, tol=p.tol, variant=MODIFIED, trunc=2)
+    assert rep["iters"] == ref.it
+    assert np.linalg.norm(x - ref.x) <= 1e-9 * np.linalg.norm(ref.x)

@@ -370,3 +370,19 @@ def test_invalid_inputs_rejected_before_device_work(torch_dev):
     b[5] = np.nan
     with pytest.raises(ecg.EcgError):
         _solve(torch, dev, p.A, b, p.part, p.t, tol=p.tol)
+
+
+@pytest.mark.parametrize("switch_tol,min_gap", [(1e-3, 5), (1e-2, 3)])
+def test_repeat_rule_parity(torch_dev, switch_tol, min_gap):
+    """Repeated halving on tol1 < switchTol, at least min_gap iterations apart, 8 -> 4 -> 2."""
+    torch, dev = torch_dev
+    p = W.config("poisson64")
+    A = p.A.to_scipy()
+    kw = dict(reduce=ora.REDUCE_REPEAT, switch_tol=switch_tol, t_min=2, min_gap=min_gap)
+    ref = ora.flexible_sre_cg2(A, p.b, p.part, p.t, tol=p.tol, **kw)
+    assert len(ref.switch_iters) == 2 and ref.t_final == 2
+    rep, x, rh = _solve(torch, dev, p.A, p.b, p.part, p.t, tol=p.tol, rho_hist=True, **kw)
+    assert rep["iters"] == ref.it and rep["switch_iters"] == ref.switch_iters and rep["t_final"] == 2
+    assert rep["vectors_stored"] == ref.mem
+    assert np.abs(rh - np.array(ref.rho)).max() <= 1e-10 * ref.rho[0]
+    assert np.linalg.norm(x - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
