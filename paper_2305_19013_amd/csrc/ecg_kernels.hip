@@ -830,10 +830,12 @@ k_final_update(int n, int nwg, const T* __restrict__ H, const T* __restrict__ Y,
 // one more 16-column tile of the B operand carries beta in its first column, so that the
 // products H beta and Y beta come out of the same instructions: x += H beta,
 // r -= Y beta, and the squared norm of the new r is reduced per workgroup.
-template <int TC>
+template <int TC, bool FINAL = false>
 struct SmallTile {
-  static constexpr int RT = TC >= 64 ? 1 : (TC == 32 ? 2 : 4);  // row tiles per wavefront
-  static constexpr int ROWS = 4 * 16 * RT;                        // rows per workgroup
+  // row tiles per wavefront; the fused update carries two products, so half as many
+  static constexpr int RT0 = TC >= 64 ? 1 : (TC == 32 ? 2 : 4);
+  static constexpr int RT = FINAL ? (RT0 > 1 ? RT0 / 2 : 1) : RT0;
+  static constexpr int ROWS = 4 * 16 * RT;  // rows per workgroup
 };
 
 template <typename T, typename TX, int TC, bool FINAL>
@@ -846,7 +848,7 @@ k_small_mfma(int n, int nwg, const T* __restrict__ H, const T* __restrict__ Yin,
   constexpr int TB = TC / 16;
   constexpr int NT = FINAL ? TB + 1 : TB;  // output column tiles (FINAL: + the beta tile)
   constexpr int LD = NT * 16;
-  constexpr int RT = SmallTile<TC>::RT;
+  constexpr int RT = SmallTile<TC, FINAL>::RT;
   __shared__ T Ms[TC * LD];
   __shared__ double red[FINAL ? kBlock : 1];
   for (int e = threadIdx.x; e < TC * LD; e += kBlock) {
@@ -858,7 +860,7 @@ k_small_mfma(int n, int nwg, const T* __restrict__ H, const T* __restrict__ Yin,
   if (blk >= nwg) return;  // uniform over the workgroup: no later barrier is split
   const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
   const int g = lane >> 4, c = lane & 15;
-  const int rowbase = blk * SmallTile<TC>::ROWS + wave * 16 * RT;
+  const int rowbase = blk * SmallTile<TC, FINAL>::ROWS + wave * 16 * RT;
   V aw[RT][NT], az[FINAL ? RT : 1][FINAL ? NT : 1];
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
@@ -1354,7 +1356,7 @@ int launch_final_update(int n, int tc, const T* H, const T* Y, const double* Cin
 #undef C
 #define C(TC)                                                                                          \
   case TC:                                                                                             \
-    nwg = cdiv(n, SmallTile<TC>::ROWS);                                                                \
+    nwg = cdiv(n, SmallTile<TC, true>::ROWS);                                                          \
     stat_begin(s);                                                                                     \
     hipLaunchKernelGGL((k_small_mfma<T, TX, TC, true>), dim3(pad8(nwg)), dim3(kBlock), 0, s, n, nwg, H, Y, \
                        Cinv, beta, Wq, Zn, x, r, part);                                                \
