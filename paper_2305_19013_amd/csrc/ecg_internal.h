@@ -11,7 +11,7 @@ namespace ecg {
 
 constexpr int kBlock = 256;      // threads per workgroup for streaming kernels
 constexpr int kMaxT = 64;        // widest block (t x t factor runs in one workgroup)
-constexpr int kSmallChunks = 1024;  // partial sums of the t x t Grams
+constexpr int kSmallChunks = 4096;  // partial sums of the t x t Grams (one wavefront each)
 
 // Device copy of a sparse matrix in CSR form (int32 row pointers).
 constexpr int kMaxDiag = 16;  // diagonal (DIA) form kept for matrices with at most this many
