@@ -18,6 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libecg.so")
+EXAMPLE = os.path.join(HERE, "examples", "poisson_solve")
 SOURCES = ["ecg_kernels.hip", "ecg_api.hip", "ecg_nn.hip", "ecg_band.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -55,6 +56,14 @@ def build(verbose: bool = False) -> str:
     if proc.returncode != 0:
         raise RuntimeError(f"link failed:\n{proc.stdout}\n{proc.stderr}")
     os.replace(tmp, LIB)
+    # a C++ program that uses the library through include/ecg.h only (no Python)
+    ex_src = os.path.join(HERE, "examples", "poisson_solve.cpp")
+    if os.path.exists(ex_src):
+        cmd = [HIPCC, "--offload-arch=gfx950", "-O2", "-I", os.path.join(ROOT, "include"), ex_src, "-L", HERE,
+               "-lecg", f"-Wl,-rpath,{HERE}", "-o", EXAMPLE]
+        proc = subprocess.run(cmd, capture_output=True, text=True)
+        if proc.returncode != 0:
+            raise RuntimeError(f"example build failed:\n{proc.stdout}\n{proc.stderr}")
     if verbose:
         print(f"built {LIB}", file=sys.stderr)
     return LIB

@@ -81,3 +81,15 @@ def test_invalid_partition_rejected(part, t, msg):
     st = L.ecg_partition_create(3, t, p.ctypes.data, 0, None, C.byref(h))
     assert st == ecg.ECG_EINVAL
     assert msg in L.ecg_last_error()
+
+
+def test_c_example_builds_against_the_header_alone():
+    """The C++ example uses only include/ecg.h and libecg.so (built by build())."""
+    exe = os.path.join(ROOT, "paper_2305_19013_amd", "examples", "poisson_solve")
+    src = exe + ".cpp"
+    text = open(src).read()
+    includes = [ln for ln in text.splitlines() if ln.startswith("#include")]
+    assert includes and all(("hip/" in ln or '"ecg.h"' in ln or "<c" in ln or "<vector>" in ln) for ln in includes)
+    assert os.path.exists(exe), "run __graft_entry__.build() first"
+    out = subprocess.run(["readelf", "-d", exe], capture_output=True, text=True).stdout
+    assert "libecg.so" in out
