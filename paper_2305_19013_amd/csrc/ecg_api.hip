@@ -721,6 +721,26 @@ ecg_status make_tri(int64_t n, const std::vector<int>& group, int ngroups, const
   if (mlU != ml) level_sets(n, group, ngroups, rpU, ciU, false, lpU, lrU, &mlU, ml);
   M->tri.ngroups = ngroups;
   M->tri.maxlev = ml;
+  {
+    std::vector<int> loc(n), fill(ngroups, 0);
+    for (int64_t i = 0; i < n; ++i) loc[i] = fill[group[i]]++;
+    M->tri.maxrows = *std::max_element(fill.begin(), fill.end());
+    if ((st = copy_in(&M->tri.loc, loc.data(), loc.size(), 0, s)) != ECG_OK) return st;
+    auto side = [&](const std::vector<int64_t>& rp, const std::vector<int32_t>& ci, const std::vector<int>& lr,
+                    int** kr, int** lcol) -> ecg_status {
+      std::vector<int> k2(2 * (size_t)n), lc(ci.size());
+      for (int64_t p = 0; p < n; ++p) {
+        k2[2 * p] = (int)rp[lr[p]];
+        k2[2 * p + 1] = (int)rp[lr[p] + 1];
+      }
+      for (size_t k = 0; k < ci.size(); ++k) lc[k] = loc[ci[k]];
+      ecg_status e;
+      if ((e = copy_in(kr, k2.data(), k2.size(), 0, s)) != ECG_OK) return e;
+      return copy_in(lcol, lc.data(), lc.size(), 0, s);
+    };
+    if ((st = side(rpL, ciL, lrL, &M->tri.kr_L, &M->tri.lcol_L)) != ECG_OK) return st;
+    if ((st = side(rpU, ciU, lrU, &M->tri.kr_U, &M->tri.lcol_U)) != ECG_OK) return st;
+  }
   if ((st = copy_in(&M->tri.lvl_ptr_L, lpL.data(), lpL.size(), 0, s)) != ECG_OK) return st;
   if ((st = copy_in(&M->tri.lvl_rows_L, lrL.data(), lrL.size(), 0, s)) != ECG_OK) return st;
   if ((st = copy_in(&M->tri.lvl_ptr_U, lpU.data(), lpU.size(), 0, s)) != ECG_OK) return st;
@@ -1086,6 +1106,11 @@ void ecg_precond_destroy(ecg_precond* M) {
   (void)hipFree(M->tri.lvl_rows_L);
   (void)hipFree(M->tri.lvl_ptr_U);
   (void)hipFree(M->tri.lvl_rows_U);
+  (void)hipFree(M->tri.loc);
+  (void)hipFree(M->tri.kr_L);
+  (void)hipFree(M->tri.kr_U);
+  (void)hipFree(M->tri.lcol_L);
+  (void)hipFree(M->tri.lcol_U);
   free_csr(M->G);
   free_csr(M->Gt);
   (void)hipFree(M->band.row_off);

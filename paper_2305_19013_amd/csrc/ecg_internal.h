@@ -147,6 +147,14 @@ struct DevTri {
   int* lvl_ptr_U = nullptr;
   int* lvl_rows_U = nullptr;
   int maxlev = 0;
+  int* loc = nullptr;  // [n] index of each row within its group (rows of a group in order)
+  int maxrows = 0;     // rows of the largest group
+  // for the LDS sweeps, per factor (L, U): the row range of the p-th row in level order
+  // (kr[2p], kr[2p+1]) and the group-local column of every entry
+  int* kr_L = nullptr;
+  int* kr_U = nullptr;
+  int* lcol_L = nullptr;
+  int* lcol_U = nullptr;
 };
 // Y = L^{-1} X (which = 0) or Y = L^{-T} X (which = 1) for row-major n x tc blocks.
 template <typename T>

@@ -955,6 +955,45 @@ k_trisolve(int which, const int* __restrict__ rp, const int* __restrict__ ci, co
   }
 }
 
+// The same sweeps with the group's solution held in LDS: grid (groups, tc / CW), a workgroup
+// owns CW columns of one group, so every dependency of a row (earlier levels of the same
+// group, the factor being block diagonal) is read from LDS instead of through L2.  Same
+// operations in the same order as k_trisolve.
+template <typename T, int CW>
+__global__ void __launch_bounds__(kBlock)
+k_trisolve_lds(int which, int tc, const int* __restrict__ kr, const int* __restrict__ lcol, const T* __restrict__ v,
+               const int* __restrict__ lptr, const int* __restrict__ lrows, int maxlev, const int* __restrict__ loc,
+               const T* __restrict__ X, T* __restrict__ Y) {
+  extern __shared__ unsigned char tri_smem[];
+  T* ys = reinterpret_cast<T*>(tri_smem);  // [rows of the group][CW]
+  const int g = blockIdx.x;
+  const int c0 = blockIdx.y * CW;
+  for (int l = 0; l < maxlev; ++l) {
+    const int p0 = lptr[g * (maxlev + 1) + l];
+    const int p1 = lptr[g * (maxlev + 1) + l + 1];
+    const int cnt = (p1 - p0) * CW;
+    for (int e = threadIdx.x; e < cnt; e += kBlock) {
+      const int p = p0 + e / CW;
+      const int c = e % CW;
+      const int row = lrows[p];
+      const int k0 = kr[2 * p], k1 = kr[2 * p + 1];
+      T s = X[(size_t)row * tc + c0 + c];
+      T d;
+      if (which == 0) {
+        for (int k = k0; k < k1 - 1; ++k) s -= v[k] * ys[lcol[k] * CW + c];
+        d = v[k1 - 1];
+      } else {
+        for (int k = k0 + 1; k < k1; ++k) s -= v[k] * ys[lcol[k] * CW + c];
+        d = v[k0];
+      }
+      const T y = s / d;
+      ys[loc[row] * CW + c] = y;
+      Y[(size_t)row * tc + c0 + c] = y;
+    }
+    __syncthreads();
+  }
+}
+
 // IC(0): rows of one group, level by level.  L's pattern is the lower triangle of A within
 // the group (diagonal last); apos[k] = position in A of L entry k.
 __global__ void __launch_bounds__(kBlock)
@@ -1374,6 +1413,35 @@ void launch_trisolve(const DevTri& M, int which, int tc, const T* X, T* Y, hipSt
   const DevCsr& F = which == 0 ? M.L : M.U;
   const int* lp = which == 0 ? M.lvl_ptr_L : M.lvl_ptr_U;
   const int* lr = which == 0 ? M.lvl_rows_L : M.lvl_rows_U;
+  // LDS-resident sweeps when one group's rows fit for at least one column (<= 128 KB)
+  constexpr size_t kTriLds = 128 * 1024;
+  int cw = 0;
+  for (int c = 8; c >= 1; c /= 2)
+    if (tc % c == 0 && (size_t)M.maxrows * c * sizeof(T) <= kTriLds) {
+      cw = c;
+      break;
+    }
+  if (M.loc && cw > 0) {
+    const int* kr = which == 0 ? M.kr_L : M.kr_U;
+    const int* lcol = which == 0 ? M.lcol_L : M.lcol_U;
+    const size_t lds = (size_t)M.maxrows * cw * sizeof(T);
+    const dim3 grid(M.ngroups, tc / cw);
+    stat_begin(s);
+    switch (cw) {
+#define C(CW)                                                                                                \
+  case CW:                                                                                                   \
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_trisolve_lds<T, CW>),                          \
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                         \
+    hipLaunchKernelGGL((k_trisolve_lds<T, CW>), grid, dim3(kBlock), lds, s, which, tc, kr, lcol, vals_of<T>(F), \
+                       lp, lr, M.maxlev, M.loc, X, Y);                                                       \
+    break;
+      C(1) C(2) C(4) C(8)
+#undef C
+    }
+    stat_end(kStatSplit, (double)F.nnz * (sizeof(T) + 4) + 4.0 * (F.n + 1) + 2.0 * sizeof(T) * F.n * tc,
+             2.0 * F.nnz * tc, s);
+    return;
+  }
   switch (tc) {
 #define C(TC)                                                                                        \
   case TC:                                                                                           \
