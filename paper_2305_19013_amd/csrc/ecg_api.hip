@@ -977,7 +977,7 @@ ecg_status build_bj_chol(const ecg_operator* A, const std::vector<int>& group, i
   if (wraw > kBandMax)
     return fail(ECG_EINVAL, "block band " + std::to_string(wraw) + " exceeds " + std::to_string(kBandMax) +
                                 " (blocks at most 128 cells wide in matrix order)");
-  const int W = std::max(kPanel, (wraw + kPanel - 1) / kPanel * kPanel);
+  const int W = wraw <= 32 ? 32 : (wraw <= 64 ? 64 : kBandMax);  // a power of two (ring index)
   const int ld = W + 1;
   std::vector<long long> ab_off(ngroups + 1, 0), panel_off(ngroups + 1, 0);
   for (int g = 0; g < ngroups; ++g) {

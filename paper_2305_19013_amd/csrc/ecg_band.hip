@@ -5,7 +5,7 @@
 //
 // Storage.  Within a block the rows keep the matrix order; the band W of a block is the
 // largest distance, in that local order, between a row and a column of A it couples to
-// (rounded up to a multiple of the panel height kPanel).  A 2D grid block of w cells per
+// (rounded up to 32, 64 or 128).  A 2D grid block of w cells per
 // grid row has W = w.  The factor is kept in column band form during the factorisation,
 // ab[j*(W+1) + d] = L[j+d][j], and then re-packed per panel of kPanel rows:
 //   [ Dinv | F | Dinv^T | B ]      Dinv = (L_pp)^{-1}                  (P x P)
@@ -136,28 +136,31 @@ k_band_panels(int W, int nblocks, const int* __restrict__ row_off, const long lo
 }
 
 // Y = L^{-1} X (FWD) or L^{-T} X for row-major n x ldx blocks; grid (nblocks, ldx / CW),
-// CW dividing ldx.
+// CW dividing ldx; the band W is a power of two (32, 64 or 128), so the ring of the last W
+// rows of Y is indexed with a mask.
 // Thread (r, c) < P*CW computes row r, column c of a panel; all kBlock threads stage the
-// panel matrices, the next one prefetched in registers while the current one is used.
-template <typename T, int CW, int WMAX, bool FWD>
+// panel matrices, the next one (and its right-hand side rows) prefetched in registers
+// while the current one is used.  In LDS the matrix rows are padded by one double so the
+// rows read by one wavefront fall on different banks.
+template <typename T, int CW, int W, bool FWD>
 __global__ void __launch_bounds__(kBlock)
-k_band_solve(int W, const int* __restrict__ row_off, const int* __restrict__ rows,
-             const long long* __restrict__ panel_off, const double* __restrict__ panels, int ldx,
-             const T* __restrict__ X, T* __restrict__ Y) {
+k_band_solve(const int* __restrict__ row_off, const int* __restrict__ rows, const long long* __restrict__ panel_off,
+             const double* __restrict__ panels, int ldx, const T* __restrict__ X, T* __restrict__ Y) {
   constexpr int P = kPanel;
-  constexpr int MW = P * (P + WMAX);
-  constexpr int NPF = (MW + kBlock - 1) / kBlock;
-  __shared__ double mat[2][MW];
+  constexpr int LDD = P + 1, LDF = W + 1;          // padded LDS row strides of Dinv and F
+  constexpr int MS = P * LDD + P * LDF;            // LDS doubles of one staged panel
+  constexpr int ME = P * (P + W);                  // doubles of one sweep's half of a record
+  constexpr int NPF = (ME + kBlock - 1) / kBlock;
+  constexpr long long PS = 2LL * P * P + 2LL * P * W;
+  __shared__ double mat[2][MS];
   __shared__ double xs[P][CW];
-  __shared__ double yw[WMAX][CW];
+  __shared__ double yw[W][CW];
   const int g = blockIdx.x;
   const int c0 = blockIdx.y * CW;
   const int ng = row_off[g + 1] - row_off[g];
   const int* rw = rows + row_off[g];
   const long long p0 = panel_off[g];
   const int npan = (int)(panel_off[g + 1] - p0);
-  const long long PS = 2LL * P * P + 2LL * P * W;
-  const int me = P * (P + W);  // elements of this sweep's half of a panel record
   const long long half = FWD ? 0 : (long long)P * (P + W);
   const int tid = threadIdx.x;
   const int r = tid / CW, c = tid % CW;
@@ -170,68 +173,85 @@ k_band_solve(int W, const int* __restrict__ row_off, const int* __restrict__ row
 #pragma unroll
     for (int q = 0; q < NPF; ++q) {
       const int e = tid + q * kBlock;
-      pf[q] = (e < me) ? src[e] : 0.0;
+      pf[q] = (e < ME) ? src[e] : 0.0;
     }
   };
   auto stash = [&](int buf) {
 #pragma unroll
     for (int q = 0; q < NPF; ++q) {
       const int e = tid + q * kBlock;
-      if (e < me) mat[buf][e] = pf[q];
+      if (e < P * P) {
+        mat[buf][(e / P) * LDD + e % P] = pf[q];
+      } else if (e < ME) {
+        const int f = e - P * P;
+        mat[buf][P * LDD + (f / W) * LDF + f % W] = pf[q];
+      }
     }
   };
+  // the right-hand side rows of a step are requested one step ahead, with its matrices
+  auto load_x = [&](int step) -> double {
+    const int i = (FWD ? step : npan - 1 - step) * P + r;
+    return (worker && i < ng) ? (double)X[(size_t)rw[i] * ldx + c0 + c] : 0.0;
+  };
+  double xcur = 0.0, xnext = 0.0;
   if (npan > 0) {
     fetch(0);
+    xcur = load_x(0);
     stash(0);
   }
   for (int step = 0; step < npan; ++step) {
     const int buf = step & 1;
     const int p = FWD ? step : npan - 1 - step;
     const int i0 = p * P;
-    if (step + 1 < npan) fetch(step + 1);
-    if (worker) xs[r][c] = (i0 + r < ng) ? (double)X[(size_t)rw[i0 + r] * ldx + c0 + c] : 0.0;
+    if (step + 1 < npan) {
+      fetch(step + 1);
+      xnext = load_x(step + 1);
+    }
+    if (worker) xs[r][c] = xcur;
     __syncthreads();  // xs, mat[buf] ready
     double acc = 0.0;
     if (worker) {
-      const double* mD = mat[buf] + r * P;           // row r of Dinv (Dinv^T)
-      const double* mF = mat[buf] + P * P + r * W;   // row r of F (B)
+      const double* mD = mat[buf] + r * LDD;             // row r of Dinv (Dinv^T)
+      const double* mF = mat[buf] + P * LDD + r * LDF;   // row r of F (B)
 #pragma unroll 8
       for (int k = 0; k < P; ++k) acc += mD[k] * xs[k][c];
       // coupling rows: FWD row i0-W+k, BWD row i0+P+k; both sit in slot (i0 [+P] + k) mod W
       const int base = FWD ? i0 : i0 + P;
-      for (int k = 0; k < W; ++k) acc -= mF[k] * yw[(base + k) % W][c];
+#pragma unroll 8
+      for (int k = 0; k < W; ++k) acc -= mF[k] * yw[(base + k) & (W - 1)][c];
     }
     __syncthreads();  // window reads done before the slots of the oldest rows are reused
     if (worker) {
-      yw[(i0 + r) % W][c] = acc;
+      yw[(i0 + r) & (W - 1)][c] = acc;
       if (i0 + r < ng) Y[(size_t)rw[i0 + r] * ldx + c0 + c] = (T)acc;
     }
     if (step + 1 < npan) stash(buf ^ 1);
+    xcur = xnext;
   }
 }
 
-template <typename T, int CW, int WMAX>
+template <typename T, int CW, int W>
 void band_launch(const DevBand& B, int which, int tc, const T* X, T* Y, hipStream_t s) {
   dim3 grid(B.nblocks, tc / CW);
   if (which == 0)
-    hipLaunchKernelGGL((k_band_solve<T, CW, WMAX, true>), grid, dim3(kBlock), 0, s, B.W, B.row_off, B.rows,
-                       B.panel_off, B.panels, tc, X, Y);
+    hipLaunchKernelGGL((k_band_solve<T, CW, W, true>), grid, dim3(kBlock), 0, s, B.row_off, B.rows, B.panel_off,
+                       B.panels, tc, X, Y);
   else
-    hipLaunchKernelGGL((k_band_solve<T, CW, WMAX, false>), grid, dim3(kBlock), 0, s, B.W, B.row_off, B.rows,
-                       B.panel_off, B.panels, tc, X, Y);
+    hipLaunchKernelGGL((k_band_solve<T, CW, W, false>), grid, dim3(kBlock), 0, s, B.row_off, B.rows, B.panel_off,
+                       B.panels, tc, X, Y);
 }
 
-template <typename T, int WMAX>
+template <typename T, int W>
 void band_dispatch_cw(const DevBand& B, int which, int tc, const T* X, T* Y, hipStream_t s) {
   // columns per workgroup: the largest of 8, 4, 2, 1 that divides tc
   if (tc % 8 == 0)
-    band_launch<T, 8, WMAX>(B, which, tc, X, Y, s);
+    band_launch<T, 8, W>(B, which, tc, X, Y, s);
   else if (tc % 4 == 0)
-    band_launch<T, 4, WMAX>(B, which, tc, X, Y, s);
+    band_launch<T, 4, W>(B, which, tc, X, Y, s);
   else if (tc % 2 == 0)
-    band_launch<T, 2, WMAX>(B, which, tc, X, Y, s);
+    band_launch<T, 2, W>(B, which, tc, X, Y, s);
   else
-    band_launch<T, 1, WMAX>(B, which, tc, X, Y, s);
+    band_launch<T, 1, W>(B, which, tc, X, Y, s);
 }
 
 }  // namespace
@@ -252,7 +272,9 @@ void launch_band_panels(const DevBand& B, const long long* ab_off, const double*
 template <typename T>
 void launch_band_solve(const DevBand& B, int which, int tc, const T* X, T* Y, hipStream_t s) {
   stat_begin(s);
-  if (B.W <= 64)
+  if (B.W == 32)
+    band_dispatch_cw<T, 32>(B, which, tc, X, Y, s);
+  else if (B.W == 64)
     band_dispatch_cw<T, 64>(B, which, tc, X, Y, s);
   else
     band_dispatch_cw<T, kBandMax>(B, which, tc, X, Y, s);

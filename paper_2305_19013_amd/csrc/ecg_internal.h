@@ -166,7 +166,7 @@ constexpr int kBandMax = 128; // widest band (multiple of kPanel)
 struct DevBand {
   int n = 0;
   int nblocks = 0;
-  int W = 0;                      // band, a multiple of kPanel, <= kBandMax
+  int W = 0;                      // band: 32, 64 or 128 (kBandMax)
   long long npanels = 0;
   int* row_off = nullptr;         // [nblocks+1] offsets into rows
   int* rows = nullptr;            // global row of every local row, block by block
