@@ -30,7 +30,8 @@ Reported:
   cpu_baseline   the FP64 oracle on the host (bounded sample, extrapolated; see 'sample')
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--t T]
-                       [--forms fp64,fp32] [--no-cpu] [--no-side] [--kmax N] [--copy-calibration]
+                       [--precond none|bj_ic0|chol64] [--forms fp64,fp32] [--no-cpu] [--no-side]
+                       [--kmax N] [--copy-calibration]
 """
 
 from __future__ import annotations
@@ -252,6 +253,9 @@ def main():
     ap.add_argument("--no-side", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--learned-ops", type=int, default=8)
+    ap.add_argument("--precond", default="none", choices=("none", "bj_ic0", "chol64"),
+                    help="preconditioner of the main solve (block-Jacobi IC(0) on the subdomains, or "
+                         "exact Cholesky of 64 blocks of a 2D grid)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="copy 1 GiB device-to-device before the solves (HBM counter calibration)")
     args = ap.parse_args()
@@ -279,9 +283,14 @@ def main():
     P = ecg.Partition(prob.part, prob.t)
     b = torch.from_numpy(prob.b).to(dev)
     forms = [f for f in args.forms.split(",") if f]
+    M = None
+    if args.precond == "bj_ic0":
+        M = ecg.Precond.bj_ic0(op, P)
+    elif args.precond == "chol64":
+        M = ecg.Precond.bj(op, W.box_partition(prob.grid, (8, 8)), ecg.BJ_CHOL)
     results = {}
     for f in forms:
-        results[f] = run_form(args, torch, ecg, prob, op, P, b, f)
+        results[f] = run_form(args, torch, ecg, prob, op, P, b, f, M=M)
     main_form = "fp64" if "fp64" in results else forms[0]
     R = results[main_form]
     rep = R["report"]
@@ -301,7 +310,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if main_form == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "n": prob.n, "nnz": prob.A.nnz, "t": prob.t,
+        "config": {"workload": args.workload, "precond": args.precond, "n": prob.n, "nnz": prob.A.nnz, "t": prob.t,
                    "reduce": {0: "none", 1: "halve once", 2: "halve repeatedly"}[prob.reduce],
                    "switch_tol": prob.switch_tol, "tol": prob.tol, "q_cols": R["q_cols"]},
         "solve": {"iters": rep["iters"], "switch_iters": rep["switch_iters"], "t_final": rep["t_final"],

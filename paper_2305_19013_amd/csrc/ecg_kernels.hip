@@ -265,6 +265,8 @@ k_gram(int n, Span<T> sp, int rows_per_chunk, const T* __restrict__ Y, T* __rest
   }
 }
 
+constexpr int kGramSplit = 32;  // first-stage sums of the Gram chunk reduction
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_reduce_chunks(long long len, int nchunks, const T* __restrict__ part, T* __restrict__ out) {
@@ -273,6 +275,20 @@ k_reduce_chunks(long long len, int nchunks, const T* __restrict__ part, T* __res
   T s = T(0);
   for (int c = 0; c < nchunks; ++c) s += part[(size_t)c * len + e];
   out[e] = s;
+}
+
+// First stage of the chunk sum: chunks [y*per, (y+1)*per) summed in order into mid[y][e]
+// (grid y = blockIdx.y), so a long chunk list is summed by many workgroups in a fixed order.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_reduce_chunks_stage(long long len, int nchunks, int per, const T* __restrict__ part, T* __restrict__ mid) {
+  const long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= len) return;
+  const int c0 = blockIdx.y * per;
+  const int c1 = min(nchunks, c0 + per);
+  T s = T(0);
+  for (int c = c0; c < c1; ++c) s += part[(size_t)c * len + e];
+  mid[(size_t)blockIdx.y * len + e] = s;
 }
 
 // ------------------------------------------------------------------ CGS2 update W -= Q G
@@ -1191,7 +1207,8 @@ static int gram_chunks(int n, int units, size_t part_cap, int m, int tc, int elt
   if (nch < want) nch = want;
   const int maxc = cdiv(n, 256);
   if (nch > maxc) nch = maxc;
-  while (nch > 1 && (size_t)nch * m * tc > part_cap) nch = (nch + 1) / 2 < nch ? (nch + 1) / 2 : nch - 1;
+  // the partials and the first-stage sums of the reduction share the buffer
+  while (nch > 1 && (size_t)(nch + kGramSplit) * m * tc > part_cap) nch = (nch + 1) / 2 < nch ? (nch + 1) / 2 : nch - 1;
   return nch < 1 ? 1 : nch;
 }
 
@@ -1244,7 +1261,17 @@ void launch_gram(int n, const Span<T>* spans, int nspan, int m, int tc, const T*
   if (nch > 1) {
     const long long len = (long long)m * tc;
     stat_begin(s);
-    hipLaunchKernelGGL((k_reduce_chunks<T>), dim3(cdiv(len, kBlock)), dim3(kBlock), 0, s, len, nch, part_buf, G);
+    if (nch > kGramSplit) {
+      // two fixed-order stages: kGramSplit partial sums of consecutive chunks, then their sum
+      const int per = cdiv(nch, kGramSplit);
+      const int nsplit = cdiv(nch, per);
+      T* mid = part_buf + (size_t)nch * len;
+      hipLaunchKernelGGL((k_reduce_chunks_stage<T>), dim3(cdiv(len, kBlock), nsplit), dim3(kBlock), 0, s, len, nch,
+                         per, part_buf, mid);
+      hipLaunchKernelGGL((k_reduce_chunks<T>), dim3(cdiv(len, kBlock)), dim3(kBlock), 0, s, len, nsplit, mid, G);
+    } else {
+      hipLaunchKernelGGL((k_reduce_chunks<T>), dim3(cdiv(len, kBlock)), dim3(kBlock), 0, s, len, nch, part_buf, G);
+    }
     stat_end(kStatGramReduce, (double)sizeof(T) * (nch + 1) * len, (double)nch * len, s);
   }
 }
