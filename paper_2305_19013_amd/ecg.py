@@ -212,6 +212,12 @@ class Operator:
     def spmv(self, x, y):
         check(lib().ecg_spmv(self.handle, _ptr(x), _ptr(y), _stream()))
 
+    def info(self):
+        """(n, nnz) as the library holds them."""
+        n, nnz = C.c_int64(), C.c_int64()
+        check(lib().ecg_operator_info(self.handle, C.byref(n), C.byref(nnz)))
+        return n.value, nnz.value
+
 
 class Partition:
     """Subdomain map part[n] in [0, t) (every subdomain non-empty)."""

@@ -386,3 +386,59 @@ def test_repeat_rule_parity(torch_dev, switch_tol, min_gap):
     assert rep["vectors_stored"] == ref.mem
     assert np.abs(rh - np.array(ref.rho)).max() <= 1e-10 * ref.rho[0]
     assert np.linalg.norm(x - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
+
+
+def test_spmv_info_and_kernel_statistics(torch_dev):
+    """ecg_spmv (FP64 y = A x), ecg_operator_info, and the per-kernel statistics: a solve of k
+    iterations records k final updates, and the byte counts are the stated algorithmic ones."""
+    torch, dev = torch_dev
+    from paper_2305_19013_amd import ecg
+
+    p = W.config("poisson64")
+    A = p.A.to_scipy()
+    op = ecg.Operator.from_csr(p.A)
+    assert op.info() == (p.n, p.A.nnz)
+    x = np.random.default_rng(3).standard_normal(p.n)
+    xt = _t(torch, dev, x)
+    yt = torch.empty_like(xt)
+    op.spmv(xt, yt)
+    assert np.abs(yt.cpu().numpy() - A @ x).max() <= 1e-14 * np.abs(A @ x).max()
+    ecg.stats_read(reset=True)
+    ecg.stats_enable(True)
+    rep, _, _ = _solve(torch, dev, p.A, p.b, p.part, p.t, tol=p.tol, kmax=11)
+    ecg.stats_enable(False)
+    st = ecg.stats_read(reset=True)
+    assert rep["iters"] == 10
+    assert st["final_update"]["count"] == 10 and st["final_update"]["ms"] > 0
+    assert st["final_update"]["bytes"] == pytest.approx(10 * (4 * 8 * p.n * p.t + p.n * (2 * 8 + 2 * 8)))
+    assert st["cgs2_gram"]["count"] == st["cgs2_update"]["count"] == 2 * 9  # two passes from k = 2 on
+
+
+def test_solve_rejects_small_or_misaligned_workspace(torch_dev):
+    """ecg_solve through the raw ABI: a workspace one byte short is ECG_ENOMEM, one not
+    256-byte aligned is ECG_EINVAL; neither touches x."""
+    torch, dev = torch_dev
+    import ctypes as C
+
+    from paper_2305_19013_amd import ecg
+
+    p = W.config("poisson64")
+    op = ecg.Operator.from_csr(p.A)
+    P = ecg.Partition(p.part, p.t)
+    o = ecg.options(tol=p.tol)
+    need = ecg.workspace_size(op, P, o)
+    ws = torch.empty(need + 512, dtype=torch.uint8, device=dev)
+    b = _t(torch, dev, p.b)
+    x = torch.full_like(b, 7.0)
+    rep = ecg.Report()
+    L = ecg.lib()
+    base = ws.data_ptr()
+    aligned = (base + 255) // 256 * 256
+    st = L.ecg_solve(op.handle, P.handle, b.data_ptr(), x.data_ptr(), C.byref(o), aligned, need - 1,
+                     ecg._stream(), C.byref(rep), None)
+    assert st == -2 and "workspace" in L.ecg_last_error().decode()
+    st = L.ecg_solve(op.handle, P.handle, b.data_ptr(), x.data_ptr(), C.byref(o), aligned + 8, need,
+                     ecg._stream(), C.byref(rep), None)
+    assert st == -1
+    torch.cuda.synchronize()
+    assert bool(torch.all(x == 7.0))
