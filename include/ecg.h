@@ -273,6 +273,15 @@ const char* ecg_last_error(void);
 /* Y = A X for a row-major n x t block (t in 1..64). */
 ecg_status ecg_debug_spmm(const ecg_operator* A, int32_t t, const double* X, double* Y,
                           void* hip_stream);
+/* Y = A X with a chosen product kernel: kernel 0 = CSR, 1 = diagonal form, 2 = grid stencil
+ * (diagonal offsets -c, -b, -a, 0, a, b, c or -c, -a, 0, a, c with b dividing c and c
+ * dividing n), -1 = the one the solver uses.  precision 0: X and Y are double, 1: float.
+ * Row-major n x t blocks, t a power of two in 1..64.  Every kernel builds a row as a chain
+ * of fused multiply-adds in the stored (CSR) or ascending-offset order, so for rows stored in
+ * ascending column order and finite X all three give bitwise equal results.  ECG_EINVAL
+ * when the operator has no such form. */
+ecg_status ecg_debug_spmm_kernel(const ecg_operator* A, int32_t kernel, int32_t precision, int32_t t,
+                                 const void* X, void* Y, void* hip_stream);
 /* out = [T^t(v)] with the map part >> level: out[i][j] = v[i] if (part[i]>>level) == j. */
 ecg_status ecg_debug_split(const ecg_partition* P, int32_t level, const double* v, double* out,
                            void* hip_stream);

@@ -605,6 +605,18 @@ ecg_status upload_dia(int64_t n, const std::vector<int64_t>& rp, const std::vect
   launch_cast_val((int)dv.size(), out->dval, out->dvalf, s);
   out->ndiag = nd;
   for (int d = 0; d < kMaxDiag; ++d) out->dia.off[d] = d < nd ? offs[d] : 0;
+  // grid stencil: offsets -c, -b, -a, 0, a, b, c (or -c, -a, 0, a, c) with b | c and c | n
+  if ((nd == 7 || nd == 5) && offs[nd / 2] == 0) {
+    bool sym = true;
+    for (int d = 0; d < nd; ++d) sym = sym && offs[d] == -offs[nd - 1 - d];
+    const long long c = offs[nd - 1], b = nd == 7 ? offs[nd - 2] : c, a = offs[nd / 2 + 1];
+    if (sym && a > 0 && c % b == 0 && n % c == 0) {
+      out->gnx = (int)b;
+      out->gny = (int)(c / b);
+      out->gnz = (int)(n / c);
+      out->ga = (int)a;
+    }
+  }
   return ECG_OK;
 }
 
@@ -1272,6 +1284,24 @@ ecg_status ecg_debug_spmm(const ecg_operator* A, int32_t t, const double* X, dou
   if (t < 1 || t > 64 || (t & (t - 1))) return fail(ECG_EINVAL, "t must be a power of two in [1, 64]");
   hipStream_t s = (hipStream_t)hip_stream;
   launch_spmm<double>(A->A, t, X, Y, s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  return ECG_OK;
+}
+
+ecg_status ecg_debug_spmm_kernel(const ecg_operator* A, int32_t kernel, int32_t precision, int32_t t, const void* X,
+                                 void* Y, void* hip_stream) {
+  if (!A || !X || !Y) return fail(ECG_EINVAL, "NULL argument");
+  if (t < 1 || t > 64 || (t & (t - 1))) return fail(ECG_EINVAL, "t must be a power of two in [1, 64]");
+  if (kernel < kSpmmAuto || kernel > kSpmmGrid) return fail(ECG_EINVAL, "unknown product kernel");
+  if (precision != 0 && precision != 1) return fail(ECG_EINVAL, "precision must be 0 (FP64) or 1 (FP32)");
+  if (kernel == kSpmmDia && A->A.ndiag == 0) return fail(ECG_EINVAL, "the operator has no diagonal form");
+  if (kernel == kSpmmGrid && A->A.gnx == 0) return fail(ECG_EINVAL, "the operator is not a grid stencil");
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (precision == 0)
+    launch_spmm<double>(A->A, t, static_cast<const double*>(X), static_cast<double*>(Y), s, kernel);
+  else
+    launch_spmm<float>(A->A, t, static_cast<const float*>(X), static_cast<float*>(Y), s, kernel);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
   return ECG_OK;

@@ -31,7 +31,16 @@ struct DevCsr {
   DiaOffsets dia{};
   double* dval = nullptr;
   float* dvalf = nullptr;
+  // grid stencil (gnx = 0 when not one): the diagonal form has the offsets
+  // -c, -b, -a, 0, a, b, c (7 diagonals) or -c, -a, 0, a, c (5, then b = c) with
+  // b = gnx, c = gnx * gny and n = gnz * c, so that row z*c + y*b + x has its +-b and +-c
+  // neighbours at (x, y +- 1, z) and (x, y, z +- 1); a = ga is any remaining offset.
+  int gnx = 0, gny = 0, gnz = 0, ga = 0;
 };
+
+// Which product kernel launch_spmm uses (the automatic choice takes the most specific one
+// the matrix has).
+enum SpmmKernel { kSpmmAuto = -1, kSpmmCsr = 0, kSpmmDia = 1, kSpmmGrid = 2 };
 
 // One contiguous run of stored blocks of equal width: block j of the span starts at
 // base + j * stride (elements); its Gram rows start at goff + j * width.
@@ -80,7 +89,7 @@ void launch_sum(const double* part, int m, double* out, hipStream_t s);
 
 // Y = A X for row-major n x tc blocks.
 template <typename T>
-void launch_spmm(const DevCsr& A, int tc, const T* X, T* Y, hipStream_t s);
+void launch_spmm(const DevCsr& A, int tc, const T* X, T* Y, hipStream_t s, int kernel = kSpmmAuto);
 
 // out = [T^{tc}(v)] with the map (part >> level); row-major n x tc (tc >= subdomain count).
 template <typename T>

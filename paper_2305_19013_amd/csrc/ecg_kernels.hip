@@ -136,7 +136,18 @@ k_gather(int nnz, const double* __restrict__ src, const int* __restrict__ perm, 
 // column indices and values first, then the eight block-row loads of X back to back, so
 // the gathers of a stencil row are all in flight together; a slot past the end of the row
 // re-reads the row's own block row with weight zero (the diagonal is always present).
-// Products are summed in the stored order of the row.
+// Products are summed in the stored order of the row, one FMA each.
+// acc += a * x, one fused multiply-add per component: all three product kernels build a row
+// as the same chain of correctly rounded FMAs in ascending column order, whatever the
+// compiler would contract on its own.
+__device__ __forceinline__ double fmac(double a, double x, double acc) { return __builtin_fma(a, x, acc); }
+__device__ __forceinline__ float fmac(float a, float x, float acc) { return __builtin_fmaf(a, x, acc); }
+template <typename T, typename V, int VL>
+__device__ __forceinline__ void fma_row(V& acc, T a, const V& x) {
+#pragma unroll
+  for (int e = 0; e < VL; ++e) acc[e] = fmac(a, x[e], acc[e]);
+}
+
 template <typename T, int TC>
 struct SpmmShape {
   static constexpr int VL = (16 / (int)sizeof(T)) < TC ? (16 / (int)sizeof(T)) : TC;  // columns per lane
@@ -172,10 +183,37 @@ k_spmm(int n, int nwg, const int* __restrict__ rp, const int* __restrict__ ci, c
 #pragma unroll
     for (int u = 0; u < KB; ++u) xv[u] = *reinterpret_cast<const Vec*>(Xc + (size_t)col[u] * TC);
 #pragma unroll
-    for (int u = 0; u < KB; ++u) acc += val[u] * xv[u];
+    for (int u = 0; u < KB; ++u) fma_row<T, Vec, S::VL>(acc, val[u], xv[u]);
   }
   *reinterpret_cast<Vec*>(Y + (size_t)row * TC + c) = acc;
 }
+
+// Coefficients of a row of the diagonal form with few instructions: of the LPR lanes that
+// share a row, lane li loads diagonals li, li + LPR, ... (coalesced along the rows) and
+// the others read them across lanes.  Each wavefront load instruction costs the memory
+// pipeline about as much for 64 broadcast values as for a 1 KB block row, so one load per
+// NL diagonals instead of one per diagonal takes most of that cost away.  Rows with fewer
+// than 4 lanes load their coefficients directly.
+template <typename T, int LPR, int MAXD>
+struct RowCoef {
+  static constexpr bool kShuffle = LPR >= 4;
+  static constexpr int NL = kShuffle ? (MAXD + LPR - 1) / LPR : MAXD;
+  T v[NL];
+  int lb;  // first lane of the row in the wavefront
+  __device__ __forceinline__ void load(const T* __restrict__ dv, int n, int nd, int row) {
+    const int li = (int)threadIdx.x % LPR;
+    lb = ((int)threadIdx.x & 63) - li;
+#pragma unroll
+    for (int j = 0; j < NL; ++j) {
+      const int d = kShuffle ? li + j * LPR : j;
+      v[j] = d < nd ? dv[(size_t)d * n + row] : T(0);
+    }
+  }
+  __device__ __forceinline__ T get(int d) const {
+    if constexpr (kShuffle) return __shfl(v[d / LPR], lb + d % LPR);
+    else return v[d];
+  }
+};
 
 // The same product for a matrix kept in diagonal form: no index loads, the ND block-row
 // gathers of a row issued together, the diagonal values read coalesced along the rows.
@@ -191,22 +229,110 @@ k_spmm_dia(int n, int nwg, int nd, DiaOffsets dia, const T* __restrict__ dv, con
   if (blk >= nwg) return;
   const int row = blk * S::RPB + (int)threadIdx.x / S::LPR;
   const int c = ((int)threadIdx.x % S::LPR) * S::VL;
-  if (row >= n) return;
+  if (row >= n) return;  // every lane of a row leaves together
   const T* __restrict__ Xc = X + c;
+  RowCoef<T, S::LPR, MAXD> coef;
+  coef.load(dv, n, nd, row);
   T val[MAXD];
   Vec xv[MAXD];
 #pragma unroll
   for (int d = 0; d < MAXD; ++d) {
     const int j = row + dia.off[d];
     const bool ok = d < nd && j >= 0 && j < n;
-    val[d] = ok ? dv[(size_t)d * n + row] : T(0);
+    const T a = coef.get(d);
+    val[d] = ok ? a : T(0);
     xv[d] = ok ? *reinterpret_cast<const Vec*>(Xc + (size_t)j * TC) : Vec(0);
   }
   Vec acc = Vec(0);
 #pragma unroll
   for (int d = 0; d < MAXD; ++d)
-    if (d < nd) acc += val[d] * xv[d];
+    if (d < nd) fma_row<T, Vec, S::VL>(acc, val[d], xv[d]);
   *reinterpret_cast<Vec*>(Y + (size_t)row * TC + c) = acc;
+}
+
+// The diagonal-form product for a grid stencil (DevCsr::gnx > 0): rows are walked as a box,
+// r = z*c + y*b + x.  A lane owns VL columns of K rows (x, y0..y0+K-1) and marches z
+// through a segment of zseg planes, keeping the block rows of planes z-1, z, z+1 in
+// registers: the +-c neighbours and, inside the K rows, the +-b ones are reused instead of
+// re-read, so a row costs about 3 + 2/K block-row loads instead of 7.  Every term is the
+// diagonal kernel's (same linear neighbour, same range test, same ascending order), so the
+// result is bitwise that of k_spmm_dia.  ND = 7 (3-D) or 5 (2-D: b = c, gny = 1, K = 1).
+template <typename T, int TC, int ND, int K>
+__global__ void __launch_bounds__(kBlock)
+k_spmm_grid(int n, int gnx, int gny, int gnz, int ga, int zseg, int nxb, int nyb, int nwork,
+            const T* __restrict__ dv, const T* __restrict__ X, T* __restrict__ Y) {
+  static_assert(ND == 7 || (ND == 5 && K == 1), "grid stencil shape");
+  using S = SpmmShape<T, TC>;
+  typedef T Vec __attribute__((ext_vector_type(S::VL)));
+  const int w = xcd_block();
+  if (w >= nwork) return;
+  // x blocks fastest: the workgroups that share halo rows run together on one XCD
+  const int bx = w % nxb, by = (w / nxb) % nyb, bz = w / (nxb * nyb);
+  const int x = bx * S::RPB + (int)threadIdx.x / S::LPR;
+  if (x >= gnx) return;  // every lane of a row leaves together
+  const T* __restrict__ Xc = X + ((int)threadIdx.x % S::LPR) * S::VL;
+  T* __restrict__ Yc = Y + ((int)threadIdx.x % S::LPR) * S::VL;
+  const int b = gnx, c = gnx * gny;
+  const int y0 = by * K;
+  const int z0 = bz * zseg, z1 = min(gnz, z0 + zseg);
+  const int rb = y0 * b + x;
+  auto ld = [&](int r) -> Vec {
+    return (r >= 0 && r < n) ? *reinterpret_cast<const Vec*>(Xc + (size_t)r * TC) : Vec(0);
+  };
+  Vec prev[K], cur[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    prev[k] = ld((z0 - 1) * c + rb + k * b);
+    cur[k] = ld(z0 * c + rb + k * b);
+  }
+  for (int z = z0; z < z1; ++z) {
+    const int r0 = z * c + rb;
+    Vec nxt[K], xm[K], xp[K], ym, yp;
+#pragma unroll
+    for (int k = 0; k < K; ++k) nxt[k] = ld(r0 + k * b + c);
+    if constexpr (ND == 7) {
+      ym = ld(r0 - b);
+      yp = ld(r0 + K * b);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      xm[k] = ld(r0 + k * b - ga);
+      xp[k] = ld(r0 + k * b + ga);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (y0 + k >= gny) break;  // the same for the whole workgroup
+      const int r = r0 + k * b;
+      RowCoef<T, S::LPR, ND> coef;
+      coef.load(dv, n, ND, r);
+      auto term = [&](int d, int j, const Vec& xv, Vec& acc) {
+        const T a = coef.get(d);
+        fma_row<T, Vec, S::VL>(acc, (j >= 0 && j < n) ? a : T(0), xv);
+      };
+      Vec acc = Vec(0);
+      if constexpr (ND == 7) {
+        term(0, r - c, prev[k], acc);
+        term(1, r - b, k > 0 ? cur[k > 0 ? k - 1 : 0] : ym, acc);
+        term(2, r - ga, xm[k], acc);
+        term(3, r, cur[k], acc);
+        term(4, r + ga, xp[k], acc);
+        term(5, r + b, k < K - 1 ? cur[k < K - 1 ? k + 1 : k] : yp, acc);
+        term(6, r + c, nxt[k], acc);
+      } else {
+        term(0, r - c, prev[k], acc);
+        term(1, r - ga, xm[k], acc);
+        term(2, r, cur[k], acc);
+        term(3, r + ga, xp[k], acc);
+        term(4, r + c, nxt[k], acc);
+      }
+      *reinterpret_cast<Vec*>(Yc + (size_t)r * TC) = acc;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      prev[k] = cur[k];
+      cur[k] = nxt[k];
+    }
+  }
 }
 
 // ------------------------------------------------------------------ split T^t
@@ -1129,24 +1255,53 @@ const double* dia_vals_of<double>(const DevCsr& A) { return A.dval; }
 template <>
 const float* dia_vals_of<float>(const DevCsr& A) { return A.dvalf; }
 
+constexpr int kGridK = 2;     // rows (y) per lane of the 3-D grid-stencil product
+constexpr int kGridZseg = 16;  // planes per workgroup of the grid-stencil product
+
+// The automatic choice.  The grid kernel pays off on 3-D stencils once a row spans at least
+// 4 lanes (so that its coefficients take one load per lane); on 2-D operators of the sizes
+// here the diagonal kernel is as fast or faster (the 2-D grid walk has too few workgroups).
+inline int spmm_choice(const DevCsr& A, int lpr) {
+  if (A.gnx > 0 && A.ndiag == 7 && lpr >= 4) return kSpmmGrid;
+  return A.ndiag > 0 ? kSpmmDia : kSpmmCsr;
+}
+
 template <typename T>
-void launch_spmm(const DevCsr& A, int tc, const T* X, T* Y, hipStream_t s) {
+void launch_spmm(const DevCsr& A, int tc, const T* X, T* Y, hipStream_t s, int kernel) {
   switch (tc) {
 #define C(TC)                                                                                    \
   case TC: {                                                                                     \
-    const int nwg = cdiv(A.n, SpmmShape<T, TC>::RPB);                                            \
+    using Sh = SpmmShape<T, TC>;                                                                 \
+    const int nwg = cdiv(A.n, Sh::RPB);                                                          \
+    if (kernel == kSpmmAuto) kernel = spmm_choice(A, Sh::LPR);                                   \
     stat_begin(s);                                                                               \
-    if (A.ndiag > 0 && A.ndiag <= 8)                                                             \
+    if (kernel == kSpmmGrid) {                                                                   \
+      const int K = A.ndiag == 7 ? kGridK : 1;                                                   \
+      const int nxb = cdiv(A.gnx, Sh::RPB), nyb = cdiv(A.gny, K), nzb = cdiv(A.gnz, kGridZseg);  \
+      const int nwork = nxb * nyb * nzb;                                                         \
+      if (A.ndiag == 7)                                                                          \
+        hipLaunchKernelGGL((k_spmm_grid<T, TC, 7, kGridK>), dim3(pad8(nwork)), dim3(kBlock), 0, s, A.n, \
+                           A.gnx, A.gny, A.gnz, A.ga, kGridZseg, nxb, nyb, nwork, dia_vals_of<T>(A), X, Y); \
+      else                                                                                       \
+        hipLaunchKernelGGL((k_spmm_grid<T, TC, 5, 1>), dim3(pad8(nwork)), dim3(kBlock), 0, s, A.n, \
+                           A.gnx, A.gny, A.gnz, A.ga, kGridZseg, nxb, nyb, nwork, dia_vals_of<T>(A), X, Y); \
+    } else if (kernel == kSpmmDia && A.ndiag == 5)                                               \
+      hipLaunchKernelGGL((k_spmm_dia<T, TC, 5>), dim3(pad8(nwg)), dim3(kBlock), 0, s, A.n, nwg, A.ndiag, \
+                         A.dia, dia_vals_of<T>(A), X, Y);                                        \
+    else if (kernel == kSpmmDia && A.ndiag == 7)                                                 \
+      hipLaunchKernelGGL((k_spmm_dia<T, TC, 7>), dim3(pad8(nwg)), dim3(kBlock), 0, s, A.n, nwg, A.ndiag, \
+                         A.dia, dia_vals_of<T>(A), X, Y);                                        \
+    else if (kernel == kSpmmDia && A.ndiag <= 8)                                                 \
       hipLaunchKernelGGL((k_spmm_dia<T, TC, 8>), dim3(pad8(nwg)), dim3(kBlock), 0, s, A.n, nwg, A.ndiag, \
                          A.dia, dia_vals_of<T>(A), X, Y);                                        \
-    else if (A.ndiag > 8)                                                                        \
+    else if (kernel == kSpmmDia)                                                                 \
       hipLaunchKernelGGL((k_spmm_dia<T, TC, kMaxDiag>), dim3(pad8(nwg)), dim3(kBlock), 0, s, A.n, nwg, \
                          A.ndiag, A.dia, dia_vals_of<T>(A), X, Y);                               \
     else                                                                                         \
       hipLaunchKernelGGL((k_spmm<T, TC>), dim3(pad8(nwg)), dim3(kBlock), 0, s, A.n, nwg, A.rowptr, \
                          A.col, vals_of<T>(A), X, Y);                                            \
-    stat_end(kStatSpmm, (A.ndiag > 0 ? (double)A.ndiag * A.n * sizeof(T)                        \
-                                     : (double)A.nnz * (sizeof(T) + 4) + 4.0 * (A.n + 1)) +     \
+    stat_end(kStatSpmm, (kernel != kSpmmCsr ? (double)A.ndiag * A.n * sizeof(T)                 \
+                                            : (double)A.nnz * (sizeof(T) + 4) + 4.0 * (A.n + 1)) + \
                             2.0 * sizeof(T) * A.n * TC,                                          \
              2.0 * A.nnz * TC, s);                                                               \
     break;                                                                                       \
@@ -1490,7 +1645,7 @@ void launch_ic0(const DevCsr& A, DevTri& M, const int* apos, int* fail, hipStrea
 
 // explicit instantiations
 #define INST(T)                                                                                          \
-  template void launch_spmm<T>(const DevCsr&, int, const T*, T*, hipStream_t);                           \
+  template void launch_spmm<T>(const DevCsr&, int, const T*, T*, hipStream_t, int);                           \
   template void launch_split<T>(int, const int*, int, int, const double*, T*, hipStream_t);             \
   template void launch_split_t<T>(int, const int*, int, int, const T*, T*, hipStream_t);                \
   template void launch_gram<T>(int, const Span<T>*, int, int, int, const T*, T*, T*, size_t, hipStream_t); \

@@ -35,7 +35,7 @@ EXPORTED = (
     "ecg_options_default", "ecg_operator_create_csr", "ecg_operator_destroy", "ecg_operator_info",
     "ecg_partition_create", "ecg_partition_destroy", "ecg_precond_create_bj_ic0", "ecg_precond_create_bj",
     "ecg_precond_create_factor", "ecg_precond_destroy", "ecg_workspace_size", "ecg_solve", "ecg_spmv",
-    "ecg_last_error", "ecg_debug_spmm", "ecg_debug_split", "ecg_debug_gram", "ecg_debug_update", "ecg_debug_gram_f32", "ecg_debug_update_f32",
+    "ecg_last_error", "ecg_debug_spmm", "ecg_debug_spmm_kernel", "ecg_debug_split", "ecg_debug_gram", "ecg_debug_update", "ecg_debug_gram_f32", "ecg_debug_update_f32",
     "ecg_debug_precond_apply", "ecg_stats_enable", "ecg_stats_read", "ecg_progress",
 )
 STAT_NAMES = ("spmm", "cgs2_gram", "cgs2_gram_reduce", "cgs2_update", "small_gram", "factor",
@@ -146,6 +146,7 @@ def lib():
             "ecg_spmv": (i32, [vp, dp, dp, vp]),
             "ecg_last_error": (C.c_char_p, []),
             "ecg_debug_spmm": (i32, [vp, i32, dp, dp, vp]),
+            "ecg_debug_spmm_kernel": (i32, [vp, i32, i32, i32, vp, vp, vp]),
             "ecg_debug_split": (i32, [vp, i32, dp, dp, vp]),
             "ecg_debug_gram": (i32, [i64, i32, i32, dp, i32, dp, dp, vp]),
             "ecg_debug_update": (i32, [i64, i32, i32, dp, i32, dp, dp, vp]),
@@ -343,6 +344,15 @@ def solve(op: Operator, part: Partition, b, x, opts: Options, workspace=None, rh
 
 def debug_spmm(op: Operator, t: int, X, Y):
     check(lib().ecg_debug_spmm(op.handle, t, _ptr(X), _ptr(Y), _stream()))
+
+
+SPMM_AUTO, SPMM_CSR, SPMM_DIA, SPMM_GRID = -1, 0, 1, 2
+
+
+def debug_spmm_kernel(op: Operator, kernel: int, t: int, X, Y):
+    """Y = A X with a chosen product kernel (SPMM_*); FP64 or FP32 tensors."""
+    prec = 1 if str(X.dtype) == "torch.float32" else 0
+    check(lib().ecg_debug_spmm_kernel(op.handle, kernel, prec, t, _ptr(X), _ptr(Y), _stream()))
 
 
 def debug_split(part: Partition, level: int, v, out):
