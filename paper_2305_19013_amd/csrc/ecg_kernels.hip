@@ -982,7 +982,7 @@ struct SmallTile {
 
 template <typename T, typename TX, int TC, bool FINAL>
 __global__ void __launch_bounds__(kBlock)
-k_small_mfma(int n, int nwg, const T* __restrict__ H, const T* __restrict__ Yin, const double* __restrict__ M,
+k_small_mfma(int n, int nwg, int ntiles, const T* __restrict__ H, const T* __restrict__ Yin, const double* __restrict__ M,
              const double* __restrict__ beta, T* __restrict__ Wout, T* __restrict__ Zout, TX* __restrict__ x,
              T* __restrict__ r, double* __restrict__ part) {
   using V = typename Mfma<T>::V;
@@ -1002,62 +1002,66 @@ k_small_mfma(int n, int nwg, const T* __restrict__ H, const T* __restrict__ Yin,
   if (blk >= nwg) return;  // uniform over the workgroup: no later barrier is split
   const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
   const int g = lane >> 4, c = lane & 15;
-  const int rowbase = blk * SmallTile<TC, FINAL>::ROWS + wave * 16 * RT;
-  V aw[RT][NT], az[FINAL ? RT : 1][FINAL ? NT : 1];
-#pragma unroll
-  for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-      aw[rt][nt] = V{0, 0, 0, 0};
-      if constexpr (FINAL) az[rt][nt] = V{0, 0, 0, 0};
-    }
-#pragma unroll
-  for (int kc = 0; kc < TC / 16; ++kc) {
-    T4 qh[RT], qy[FINAL ? RT : 1];
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt) {
-      const int row = rowbase + rt * 16 + c;
-      const size_t off = (size_t)row * TC + kc * 16 + 4 * g;
-      qh[rt] = row < n ? *reinterpret_cast<const T4*>(H + off) : T4{0, 0, 0, 0};
-      if constexpr (FINAL) qy[rt] = row < n ? *reinterpret_cast<const T4*>(Yin + off) : T4{0, 0, 0, 0};
-    }
-#pragma unroll
-    for (int s4 = 0; s4 < 4; ++s4) {
-      const int kk = kc * 16 + 4 * g + s4;
-      T gv[NT];
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) gv[nt] = Ms[kk * LD + nt * 16 + c];
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-          aw[rt][nt] = Mfma<T>::run(qh[rt][s4], gv[nt], aw[rt][nt]);
-          if constexpr (FINAL) az[rt][nt] = Mfma<T>::run(qy[rt][s4], gv[nt], az[rt][nt]);
-        }
-    }
-  }
   double rr = 0.0;
+  // row tiles blk, blk + nwg, ...: M is staged once per workgroup, and the partial norm of
+  // a workgroup sums its tiles in that fixed order
+  for (int tile = blk; tile < ntiles; tile += nwg) {
+    const int rowbase = tile * SmallTile<TC, FINAL>::ROWS + wave * 16 * RT;
+    V aw[RT][NT], az[FINAL ? RT : 1][FINAL ? NT : 1];
 #pragma unroll
-  for (int rt = 0; rt < RT; ++rt)
+    for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int row = rowbase + rt * 16 + Mfma<T>::row(g, v);
-      if (row < n) {
+      for (int nt = 0; nt < NT; ++nt) {
+        aw[rt][nt] = V{0, 0, 0, 0};
+        if constexpr (FINAL) az[rt][nt] = V{0, 0, 0, 0};
+      }
 #pragma unroll
-        for (int tb = 0; tb < TB; ++tb) {
-          Wout[(size_t)row * TC + tb * 16 + c] = aw[rt][tb][v];
-          if constexpr (FINAL) Zout[(size_t)row * TC + tb * 16 + c] = az[rt][tb][v];
-        }
-        if constexpr (FINAL) {
-          if (c == 0) {  // column 0 of the beta tile: (H beta)_row and (Y beta)_row
-            x[row] += (TX)aw[rt][TB][v];
-            const T rn = r[row] - az[rt][TB][v];
-            r[row] = rn;
-            rr += (double)rn * (double)rn;
+    for (int kc = 0; kc < TC / 16; ++kc) {
+      T4 qh[RT], qy[FINAL ? RT : 1];
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        const int row = rowbase + rt * 16 + c;
+        const size_t off = (size_t)row * TC + kc * 16 + 4 * g;
+        qh[rt] = row < n ? *reinterpret_cast<const T4*>(H + off) : T4{0, 0, 0, 0};
+        if constexpr (FINAL) qy[rt] = row < n ? *reinterpret_cast<const T4*>(Yin + off) : T4{0, 0, 0, 0};
+      }
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const int kk = kc * 16 + 4 * g + s4;
+        T gv[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) gv[nt] = Ms[kk * LD + nt * 16 + c];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) {
+            aw[rt][nt] = Mfma<T>::run(qh[rt][s4], gv[nt], aw[rt][nt]);
+            if constexpr (FINAL) az[rt][nt] = Mfma<T>::run(qy[rt][s4], gv[nt], az[rt][nt]);
+          }
+      }
+    }
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = rowbase + rt * 16 + Mfma<T>::row(g, v);
+        if (row < n) {
+#pragma unroll
+          for (int tb = 0; tb < TB; ++tb) {
+            Wout[(size_t)row * TC + tb * 16 + c] = aw[rt][tb][v];
+            if constexpr (FINAL) Zout[(size_t)row * TC + tb * 16 + c] = az[rt][tb][v];
+          }
+          if constexpr (FINAL) {
+            if (c == 0) {  // column 0 of the beta tile: (H beta)_row and (Y beta)_row
+              x[row] += (TX)aw[rt][TB][v];
+              const T rn = r[row] - az[rt][TB][v];
+              r[row] = rn;
+              rr += (double)rn * (double)rn;
+            }
           }
         }
       }
-    }
+  }
   if constexpr (FINAL) {
     const double tot = block_sum(rr, red);
     if (threadIdx.x == 0) part[blk] = tot;
@@ -1550,7 +1554,7 @@ void launch_times_small(int n, int tc, const T* X, const double* M, T* out, hipS
 #define C(TC)                                                                                         \
   case TC: {                                                                                          \
     const int nwg = cdiv(n, SmallTile<TC>::ROWS);                                                     \
-    hipLaunchKernelGGL((k_small_mfma<T, double, TC, false>), dim3(pad8(nwg)), dim3(kBlock), 0, s, n, nwg, X, \
+    hipLaunchKernelGGL((k_small_mfma<T, double, TC, false>), dim3(pad8(nwg)), dim3(kBlock), 0, s, n, nwg, nwg, X, \
                        nullptr, M, nullptr, out, nullptr, nullptr, nullptr, nullptr);                 \
     break;                                                                                            \
   }
@@ -1559,10 +1563,12 @@ void launch_times_small(int n, int tc, const T* X, const double* M, T* out, hipS
   }
 }
 
+constexpr int kFinalGroups = 2048;  // workgroups of the fused update (8 per CU)
+
 template <typename T, typename TX>
 int launch_final_update(int n, int tc, const T* H, const T* Y, const double* Cinv, const double* beta, T* Wq,
                         T* Zn, TX* x, T* r, double* part, hipStream_t s) {
-  int nwg = 0;
+  int nwg = 0, ntiles = 0;
   switch (tc) {
 #define C(TC)                                                                                          \
   case TC:                                                                                             \
@@ -1577,9 +1583,10 @@ int launch_final_update(int n, int tc, const T* H, const T* Y, const double* Cin
 #undef C
 #define C(TC)                                                                                          \
   case TC:                                                                                             \
-    nwg = cdiv(n, SmallTile<TC, true>::ROWS);                                                          \
+    ntiles = cdiv(n, SmallTile<TC, true>::ROWS);                                                       \
+    nwg = std::min(ntiles, kFinalGroups);                                                              \
     stat_begin(s);                                                                                     \
-    hipLaunchKernelGGL((k_small_mfma<T, TX, TC, true>), dim3(pad8(nwg)), dim3(kBlock), 0, s, n, nwg, H, Y, \
+    hipLaunchKernelGGL((k_small_mfma<T, TX, TC, true>), dim3(pad8(nwg)), dim3(kBlock), 0, s, n, nwg, ntiles, H, Y, \
                        Cinv, beta, Wq, Zn, x, r, part);                                                \
     stat_end(kStatFinal, 4.0 * sizeof(T) * n * TC + (double)n * (2 * sizeof(TX) + 2 * sizeof(T)),      \
              4.0 * n * TC * TC + 4.0 * n * TC, s);                                                     \
