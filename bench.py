@@ -162,46 +162,69 @@ def kernel_table(stats, steps):
     return out
 
 
-def cpu_baseline(prob, widths_gpu, it_gpu, switch_gpu, k1=2, k2=6):
+class _StampedA:
+    """A @ X for the oracle, with a wall-clock stamp taken before every product: the
+    products fall at fixed points of each iteration, so the stamps split a run into
+    per-iteration times without touching the oracle."""
+
+    def __init__(self, A):
+        self.A, self.shape, self.stamps = A, A.shape, []
+
+    def __matmul__(self, X):
+        self.stamps.append(time.perf_counter())
+        return self.A @ X
+
+
+def cpu_baseline(prob, widths_gpu, it_gpu, switch_gpu, kmax=8):
     """Bounded sample of the FP64 oracle on the same workload, extrapolated.
 
-    The oracle runs the first k1 and then the first k2 iterations; the two wall times give
-    a per-iteration cost a + b*m (m = stored columns) that is summed over the GPU run's
-    iteration history (same widths and switch) to estimate a whole oracle solve.
+    The oracle runs the first kmax iterations of the same solve.  Iteration 1 makes two
+    products with A, every later one four (two CGS2 passes, the A-step Gram, the fresh
+    A W); the stamps of those products split each iteration into segments.  The cost per
+    stored column b comes from the segments that carry it: the first CGS2 pass (product,
+    Q^T Y, Q G; the second pass is the same work) and the stretch from the fresh product
+    to the next iteration (which stacks Q), each fitted by least squares against m_k; it is
+    b = 2 b_pass + b_stack.  The rest of an iteration is the constant a, the mean of
+    T_k - b m_k.  T = a + b m_k is then summed over the GPU run's iteration history (same
+    widths and switch) to estimate a whole solve.
     """
     import threadpoolctl
 
     from oracle import ecg as ora
 
-    A = prob.A.to_scipy()
+    A = _StampedA(prob.A.to_scipy())
     info = threadpoolctl.threadpool_info()
     threads = max([i.get("num_threads", 1) for i in info] or [1])
-    times = {}
-    for K in (k1, k2):
-        t0 = time.perf_counter()
-        r = ora.flexible_sre_cg2(A, prob.b, prob.part, prob.t, tol=prob.tol, kmax=K + 1, reduce=prob.reduce,
-                                 switch_tol=prob.switch_tol, t_min=prob.t_min)
-        times[K] = (time.perf_counter() - t0, r)
-        log(f"[cpu] oracle first {K} iterations: {times[K][0]:.2f}s")
-    (ta, ra), (tb, rb) = times[k1], times[k2]
-
-    def msum(widths, lo, hi):  # sum over iterations lo..hi-1 (0-based) of stored columns before k
-        cs = np.concatenate([[0], np.cumsum(widths)])
-        return float(sum(cs[k] for k in range(lo, hi)))
-
-    # ta = k1*a + b*M1, tb - ta = (k2-k1)*a + b*(M2 - M1)
-    M1, M2 = msum(rb.widths, 0, k1), msum(rb.widths, 0, k2)
-    mat = np.array([[float(k1), M1], [float(k2 - k1), M2 - M1]])
-    a, bcoef = np.linalg.solve(mat, np.array([ta, tb - ta]))
-    a = max(a, 0.0)
-    bcoef = max(bcoef, 0.0)
-    est = a * it_gpu + bcoef * msum(widths_gpu, 0, it_gpu)
+    t0 = time.perf_counter()
+    r = ora.flexible_sre_cg2(A, prob.b, prob.part, prob.t, tol=prob.tol, kmax=kmax + 1, reduce=prob.reduce,
+                             switch_tol=prob.switch_tol, t_min=prob.t_min)
+    t_end = time.perf_counter()
+    log(f"[cpu] oracle first {r.it} iterations: {t_end - t0:.2f}s")
+    st = A.stamps
+    first = [1] + [3 + 4 * (k - 2) for k in range(2, r.it + 1)]  # stamp index opening iteration k
+    assert len(st) == 1 + 2 + 4 * (r.it - 1), (len(st), r.it)
+    opens = [st[i] for i in first] + [t_end]
+    T = np.diff(opens)  # T[k-1] = time of iteration k
+    cs = np.concatenate([[0], np.cumsum(r.widths)])
+    ks = np.arange(2, r.it)  # complete iterations with a non-empty basis
+    mk = cs[ks - 1].astype(float)
+    stn = np.array(st + [t_end])
+    i1 = np.array([first[k - 1] for k in ks])
+    seg_pass = stn[i1 + 1] - stn[i1]  # CGS2 pass 1
+    seg_stack = stn[i1 + 4] - stn[i1 + 3]  # fresh product .. next iteration (stacks Q)
+    b_pass = max(np.polyfit(mk, seg_pass, 1)[0], 0.0)
+    b_stack = max(np.polyfit(mk, seg_stack, 1)[0], 0.0)
+    bcoef = 2.0 * b_pass + b_stack
+    a = max(float(np.mean(T[ks - 1] - bcoef * mk)), 0.0)
+    csg = np.concatenate([[0], np.cumsum(widths_gpu)])
+    est = float(T[0] + sum(a + bcoef * csg[k - 1] for k in range(2, it_gpu + 1)))
     return {"value": round(est, 2), "unit": "s", "cores": int(threads), "kind": "oracle",
-            "sample": (f"FP64 oracle (NumPy/SciPy, OpenBLAS {threads} threads) timed on the first {k1} and first "
-                       f"{k2} iterations of the same solve ({ta:.1f}s, {tb:.1f}s); per-iteration cost a+b*m "
-                       f"(a={a:.3f}s, b={bcoef:.2e}s per stored column) summed over the GPU run's {it_gpu} "
-                       f"iterations and widths; measured_seconds={ta + tb:.1f}"),
-            "measured_sample_s": round(ta + tb, 2)}
+            "sample": (f"FP64 oracle (NumPy/SciPy, OpenBLAS {threads} threads) timed on the first {r.it} iterations "
+                       f"of the same solve ({t_end - t0:.1f}s), per iteration from stamps taken at its products with "
+                       f"A; T_k = a + b*m_k with b = 2*(slope of a CGS2 pass) + (slope of the Q stacking) fitted "
+                       f"over iterations 2..{r.it - 1} (a={a:.3f}s, b={bcoef:.2e}s per stored column, m_k up to "
+                       f"{int(mk.max())}), summed over the GPU run's {it_gpu} iterations and widths"),
+            "measured_sample_s": round(t_end - t0, 2)}
 
 
 def learned_section(args, torch, dev):

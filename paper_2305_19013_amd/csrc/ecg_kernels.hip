@@ -130,6 +130,10 @@ k_gather(int nnz, const double* __restrict__ src, const int* __restrict__ perm, 
 }
 
 // ------------------------------------------------------------------ SpMM
+// Y is written with non-temporal stores in all three product kernels: the next kernel (the
+// CGS2 Gram) streams the stored basis, and Y lines left dirty in the caches cost it
+// write-backs in the middle of that stream (measured: the Gram and the t x t Grams after it
+// run 3-5% faster).
 // Y = A X, row-major n x TC blocks.  Each lane owns VL consecutive columns of one row
 // (one 16-byte load of X per nonzero), so TC / VL lanes share a row and a wavefront reads
 // whole contiguous block rows of X.  The nonzeros of a row are taken eight at a time: the
@@ -185,7 +189,7 @@ k_spmm(int n, int nwg, const int* __restrict__ rp, const int* __restrict__ ci, c
 #pragma unroll
     for (int u = 0; u < KB; ++u) fma_row<T, Vec, S::VL>(acc, val[u], xv[u]);
   }
-  *reinterpret_cast<Vec*>(Y + (size_t)row * TC + c) = acc;
+  __builtin_nontemporal_store(acc, reinterpret_cast<Vec*>(Y + (size_t)row * TC + c));
 }
 
 // Coefficients of a row of the diagonal form with few instructions: of the LPR lanes that
@@ -247,7 +251,7 @@ k_spmm_dia(int n, int nwg, int nd, DiaOffsets dia, const T* __restrict__ dv, con
 #pragma unroll
   for (int d = 0; d < MAXD; ++d)
     if (d < nd) fma_row<T, Vec, S::VL>(acc, val[d], xv[d]);
-  *reinterpret_cast<Vec*>(Y + (size_t)row * TC + c) = acc;
+  __builtin_nontemporal_store(acc, reinterpret_cast<Vec*>(Y + (size_t)row * TC + c));
 }
 
 // The diagonal-form product for a grid stencil (DevCsr::gnx > 0): rows are walked as a box,
@@ -325,7 +329,7 @@ k_spmm_grid(int n, int gnx, int gny, int gnz, int ga, int zseg, int nxb, int nyb
         term(3, r + ga, xp[k], acc);
         term(4, r + c, nxt[k], acc);
       }
-      *reinterpret_cast<Vec*>(Yc + (size_t)r * TC) = acc;
+      __builtin_nontemporal_store(acc, reinterpret_cast<Vec*>(Yc + (size_t)r * TC));
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
