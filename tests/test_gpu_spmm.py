@@ -151,3 +151,23 @@ def test_grid_stencil_full_size_equals_diagonal_form(torch_dev, t):
         ecg.debug_spmm_kernel(op, DIA_K, t, Xt, Yd)
         torch.cuda.synchronize()
         assert bool(torch.equal(Yg, Yd))
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_fp32_refined_solve_on_3d_stencil(torch_dev, variant):
+    """The FP32 form on a 3-D 7-point operator (32^3 anisotropic, t = 32 -> 16), so that its
+    products run on the FP32 grid-stencil kernel; SRE-CG2 and MSDO-CG: the FP64 true
+    residual recomputed on the host reaches 1e-8."""
+    torch, dev = torch_dev
+    from oracle import ecg as ora
+    from paper_2305_19013_amd import ecg
+
+    p = W.config("aniso3d128", scale=4)
+    op = ecg.Operator.from_csr(p.A)
+    P = ecg.Partition(p.part, p.t)
+    bt = torch.from_numpy(p.b).to(dev)
+    xt = torch.zeros_like(bt)
+    rep, _ = ecg.solve(op, P, bt, xt, ecg.options(tol=1e-8, precision=1, inner_tol=1e-4, variant=variant,
+                                                  reduce=p.reduce, switch_tol=p.switch_tol, t_min=p.t_min))
+    assert rep["status"] == "ok"
+    assert ora.true_relres(p.A.to_scipy(), p.b, xt.cpu().numpy()) <= 1.01e-8
