@@ -139,8 +139,9 @@ k_band_panels(int W, int nblocks, const int* __restrict__ row_off, const long lo
 // CW dividing ldx; the band W is a power of two (32, 64 or 128), so the ring of the last W
 // rows of Y is indexed with a mask.
 // Thread (r, c) < P*CW computes row r, column c of a panel; all kBlock threads stage the
-// panel matrices, the next one (and its right-hand side rows) prefetched in registers
-// while the current one is used.  In LDS the matrix rows are padded by one double so the
+// panel matrices, those of the next two steps (and their right-hand side rows) held in
+// registers while the current one is used: a step is shorter than one round trip to
+// memory, so one step of look-ahead left the sweep waiting on its loads.  In LDS the matrix rows are padded by one double so the
 // rows read by one wavefront fall on different banks.
 template <typename T, int CW, int W, bool FWD>
 __global__ void __launch_bounds__(kBlock)
@@ -166,8 +167,10 @@ k_band_solve(const int* __restrict__ row_off, const int* __restrict__ rows, cons
   const int r = tid / CW, c = tid % CW;
   const bool worker = tid < P * CW;
   for (int e = tid; e < W * CW; e += kBlock) yw[e / CW][e % CW] = 0.0;
-  double pf[NPF];
-  auto fetch = [&](int step) {
+  // the matrices (and right-hand side rows) of a step are requested two steps ahead, into
+  // one of two register buffers: even steps use pfa / xa, odd steps pfb / xb
+  double pfa[NPF], pfb[NPF];
+  auto fetch = [&](double (&pf)[NPF], int step) {
     const int p = FWD ? step : npan - 1 - step;
     const double* src = panels + (p0 + p) * PS + half;
 #pragma unroll
@@ -176,7 +179,7 @@ k_band_solve(const int* __restrict__ row_off, const int* __restrict__ rows, cons
       pf[q] = (e < ME) ? src[e] : 0.0;
     }
   };
-  auto stash = [&](int buf) {
+  auto stash = [&](const double (&pf)[NPF], int buf) {
 #pragma unroll
     for (int q = 0; q < NPF; ++q) {
       const int e = tid + q * kBlock;
@@ -188,24 +191,36 @@ k_band_solve(const int* __restrict__ row_off, const int* __restrict__ rows, cons
       }
     }
   };
-  // the right-hand side rows of a step are requested one step ahead, with its matrices
-  auto load_x = [&](int step) -> double {
+  // the right-hand side value of row i0 + r and that row's global index, which the step
+  // also needs for its store of Y
+  auto load_x = [&](int step, double& xv, int& gi) {
     const int i = (FWD ? step : npan - 1 - step) * P + r;
-    return (worker && i < ng) ? (double)X[(size_t)rw[i] * ldx + c0 + c] : 0.0;
+    gi = (worker && i < ng) ? rw[i] : -1;
+    xv = gi >= 0 ? (double)X[(size_t)gi * ldx + c0 + c] : 0.0;
   };
-  double xcur = 0.0, xnext = 0.0;
+  double xa = 0.0, xb = 0.0;
+  int ga = -1, gb = -1;
   if (npan > 0) {
-    fetch(0);
-    xcur = load_x(0);
-    stash(0);
+    fetch(pfa, 0);
+    load_x(0, xa, ga);
+    stash(pfa, 0);
   }
-  for (int step = 0; step < npan; ++step) {
+  if (npan > 1) {
+    fetch(pfb, 1);
+    load_x(1, xb, gb);
+  }
+  // one step: its matrices are in mat[step & 1] and its right-hand side in x_mine; the
+  // buffers pf_mine / x_mine are free again and take step + 2, and pf_next (step + 1) is
+  // staged at the end
+  auto body = [&](int step, double (&pf_mine)[NPF], double& x_mine, int& g_mine, const double (&pf_next)[NPF]) {
     const int buf = step & 1;
     const int p = FWD ? step : npan - 1 - step;
     const int i0 = p * P;
-    if (step + 1 < npan) {
-      fetch(step + 1);
-      xnext = load_x(step + 1);
+    const double xcur = x_mine;
+    const int gcur = g_mine;
+    if (step + 2 < npan) {
+      fetch(pf_mine, step + 2);
+      load_x(step + 2, x_mine, g_mine);
     }
     if (worker) xs[r][c] = xcur;
     __syncthreads();  // xs, mat[buf] ready
@@ -223,10 +238,13 @@ k_band_solve(const int* __restrict__ row_off, const int* __restrict__ rows, cons
     __syncthreads();  // window reads done before the slots of the oldest rows are reused
     if (worker) {
       yw[(i0 + r) & (W - 1)][c] = acc;
-      if (i0 + r < ng) Y[(size_t)rw[i0 + r] * ldx + c0 + c] = (T)acc;
+      if (gcur >= 0) Y[(size_t)gcur * ldx + c0 + c] = (T)acc;
     }
-    if (step + 1 < npan) stash(buf ^ 1);
-    xcur = xnext;
+    if (step + 1 < npan) stash(pf_next, buf ^ 1);  // mat[buf ^ 1] was last read before the first barrier
+  };
+  for (int step = 0; step < npan; step += 2) {
+    body(step, pfa, xa, ga, pfb);
+    if (step + 1 < npan) body(step + 1, pfb, xb, gb, pfa);
   }
 }
 
