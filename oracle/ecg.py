@@ -268,6 +268,19 @@ def _switch_now(rule, k, tol1, switch_tol, t_cur, t_min, switches, min_gap, sche
     raise ValueError(rule)
 
 
+def _check_halving(t, rule, t_min, schedule):
+    """A halving merges subdomains 2i and 2i+1 (Section 4), so each width the rule may halve
+    (down to t_min) must be even; raises ValueError otherwise."""
+    steps = {REDUCE_NONE: 0, REDUCE_ONCE: 1, REDUCE_REPEAT: 64, REDUCE_SCHEDULE: len(schedule)}[rule]
+    w = t
+    for _ in range(steps):
+        if w // 2 < max(t_min, 1):
+            break
+        if w % 2:
+            raise ValueError(f"halving requested at odd block width {w}")
+        w //= 2
+
+
 def _restart_now(rule, k, tol1, every, restart_tol, restarts, max_restarts):
     if rule == RESTART_NONE:
         return False
@@ -303,6 +316,7 @@ def flexible_sre_cg2(A, b, part, t, *, x0=None, tol=1e-8, kmax=20000, reduce=RED
                     t_final=t, deflated=0)
     if rho0 == 0.0:
         return res
+    _check_halving(t, reduce, t_min, list(schedule))
     schedule = set(int(s) for s in schedule)
     rho_prev = rho0
     tol1 = 1.0
@@ -449,6 +463,7 @@ def flexible_msdo_cg(A, b, part, t, *, x0=None, tol=1e-8, kmax=20000, reduce=RED
                     t_final=t, deflated=0)
     if rho0 == 0.0:
         return res
+    _check_halving(t, reduce, t_min, list(schedule))
     schedule = set(int(s) for s in schedule)
     pre = precond
     rho_prev, tol1, k, level, t_cur = rho0, 1.0, 1, 0, t

@@ -160,8 +160,9 @@ ecg_status make_plan(int64_t n, int t, const ecg_options& o, Plan* p) {
     return at;
   };
   const size_t small_len = (size_t)tp * tp + tp;
+  const size_t small_chunks = std::min<size_t>(kSmallChunks, ((size_t)n + 255) / 256);
   p->off_status = take(sizeof(IterStatus));
-  p->off_small_part = take(((size_t)kSmallChunks + 32) * small_len * 8);  // chunks + stage-2 rows
+  p->off_small_part = take((small_chunks + 32) * small_len * 8);  // chunks + stage-2 rows
   p->off_small_out = take(small_len * 8);
   p->off_ref = take(small_len * 8);  // candidate Gram before CGS2 / MSDO's V^T r
   p->off_rinv = take((size_t)tp * tp * 8);
@@ -169,7 +170,10 @@ ecg_status make_plan(int64_t n, int t, const ecg_options& o, Plan* p) {
   p->off_beta = take((size_t)tp * 8);
   p->off_norm_part = take(((size_t)n / 4 + 64 + 128) * 8);  // partials + stage-2 slices
   p->off_scalar = take(64 * 8);
-  p->gram_part_cap = (size_t)1 << 26;  // elements: partial Gram sums of the row chunks
+  // elements: partial Gram sums of the row chunks (at most one chunk per 256 rows) and the
+  // first-stage sums of their reduction, capped at 2^26; the launcher uses fewer chunks when
+  // they would not fit
+  p->gram_part_cap = std::min<size_t>((size_t)1 << 26, ((size_t)n / 256 + 1 + 32) * (size_t)cap * tp);
   p->off_gram_part = take(p->gram_part_cap * p->elt);
   p->off_G = take((size_t)cap * tp * p->elt);
   p->off_C = take(slot_bytes);
@@ -206,6 +210,19 @@ ecg_status check_options(const ecg_options* o) {
   if (o->restart < ECG_RESTART_NONE || o->restart > ECG_RESTART_TOL) return fail(ECG_EINVAL, "unknown restart rule");
   if (o->restart == ECG_RESTART_EVERY && o->restart_every < 1) return fail(ECG_EINVAL, "restart_every must be >= 1");
   if (o->max_restarts < 0) return fail(ECG_EINVAL, "max_restarts must be >= 0");
+  return ECG_OK;
+}
+
+// A halving merges subdomains 2i and 2i+1 (Section 4), so every width that is halved must be
+// even: the halvings the rule can make (down to t_min) are checked before any device work.
+ecg_status check_halving(int t, const ecg_options& o) {
+  const int tmin = std::max(o.t_min, 1);
+  int steps = 0;
+  if (o.reduce == ECG_REDUCE_SWITCHTOL_ONCE) steps = 1;
+  else if (o.reduce == ECG_REDUCE_SWITCHTOL_REPEAT) steps = 64;
+  else if (o.reduce == ECG_REDUCE_SCHEDULE) steps = o.n_schedule;
+  for (int w = t, i = 0; i < steps && w / 2 >= tmin; ++i, w /= 2)
+    if (w % 2) return fail(ECG_EINVAL, "halving requested at odd block width " + std::to_string(w));
   return ECG_OK;
 }
 
@@ -473,7 +490,7 @@ ecg_status ecg_inner(const ecg_operator* Aop, const ecg_partition* P, const ecg_
     HIPCHK(hipMemcpyAsync(&hst, st, sizeof(IterStatus), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     HIPCHK(hipGetLastError());
-    if (g_stats_on) flush_stats();
+    if (g_stats_on && g_pending.size() >= 4096) flush_stats();  // every recorded event has completed
     if (hst.breakdown) {
       res->status = ECG_EBREAKDOWN;
       g_err = "non-positive pivot in the t x t Cholesky with deflation disabled";
@@ -1163,6 +1180,9 @@ ecg_status ecg_solve(const ecg_operator* A, const ecg_partition* P, const double
     return fail(ECG_EINVAL, "preconditioner size differs from the operator");
   if (o->precond == ECG_PRECOND_SPLIT && o->M->kind == 0 && o->M->tri.L.n != A->n)
     return fail(ECG_EINVAL, "preconditioner size differs from the operator");
+  if (o->precond == ECG_PRECOND_SPLIT && o->M->kind == 2 && o->M->band.n != A->n)
+    return fail(ECG_EINVAL, "preconditioner size differs from the operator");
+  if ((st = check_halving(P->t, *o)) != ECG_OK) return st;
   Plan pl;
   if ((st = make_plan(A->n, P->t, *o, &pl)) != ECG_OK) return st;
   if (ws_bytes < pl.total) return fail(ECG_ENOMEM, "workspace too small: need " + std::to_string(pl.total) + " bytes");

@@ -322,6 +322,10 @@ def solve(op: Operator, part: Partition, b, x, opts: Options, workspace=None, rh
     """
     import torch
 
+    for name, v in (("b", b), ("x", x)):
+        if not (isinstance(v, torch.Tensor) and v.is_cuda and v.dtype == torch.float64 and v.dim() == 1
+                and v.is_contiguous() and v.numel() == op.n):
+            raise ValueError(f"{name} must be a contiguous float64 CUDA tensor of length n = {op.n}")
     need = workspace_size(op, part, opts)
     if workspace is None:
         workspace = torch.empty(need, dtype=torch.uint8, device=b.device)

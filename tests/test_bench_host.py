@@ -20,11 +20,21 @@ def test_oracle_makes_two_then_four_products_per_iteration():
     assert np.all(np.diff(A.stamps) >= 0)
 
 
-def test_cpu_baseline_extrapolates_from_a_short_run():
+def test_cpu_baseline_from_a_short_run_and_a_cgs2_probe():
     p = W.config("aniso3d128", scale=8)  # 16^3, t = 32
     widths = [32] * 10 + [16] * 20
-    out = bench.cpu_baseline(p, widths, 30, [10], kmax=5)
+    out = bench.cpu_baseline(p, widths, kmax=5, m_probe=(64, 256))
     assert out["kind"] == "oracle" and out["unit"] == "s" and out["cores"] >= 1
     assert out["value"] > 0 and out["measured_sample_s"] > 0
-    # the estimate sums 30 iterations of at least the constant cost fitted on 5
-    assert "first 5 iterations" in out["sample"]
+    assert out["per_column_s"] >= 0 and out["per_iteration_const_s"] >= 0
+    assert "first 4 iterations" in out["sample"] and "m=256" in out["sample"]
+    # the estimate covers all 30 iterations: at least 29 times the constant part
+    assert out["value"] >= 29 * out["per_iteration_const_s"]
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+
+    r = subprocess.run([sys.executable, bench.__file__, "--gpus", "2"], capture_output=True, text=True)
+    assert r.returncode == 2 and "one GPU" in r.stderr

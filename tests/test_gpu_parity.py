@@ -442,3 +442,40 @@ def test_solve_rejects_small_or_misaligned_workspace(torch_dev):
     assert st == -1
     torch.cuda.synchronize()
     assert bool(torch.all(x == 7.0))
+
+
+def test_mismatched_preconditioner_odd_halving_and_bad_tensors_rejected(torch_dev):
+    """Host-side checks before any kernel: a band-Cholesky preconditioner built on another
+    operator size, a halving of an odd width (subdomains merge in pairs, Section 4), and
+    vectors that are not contiguous float64 device tensors of length n."""
+    torch, dev = torch_dev
+    from paper_2305_19013_amd import ecg
+
+    p = W.config("poisson64")
+    small = W.config("poisson64", scale=2)  # 32 x 32
+    op_small = ecg.Operator.from_csr(small.A)
+    M_small = ecg.Precond.bj(op_small, W.box_partition(small.grid, (4, 4)), ecg.BJ_CHOL)
+    with pytest.raises(ecg.EcgError) as e:
+        _solve(torch, dev, p.A, p.b, p.part, p.t, tol=p.tol, M=M_small)
+    assert e.value.status == ecg.ECG_EINVAL
+    n = 60
+    A = W.random_spd(n, 30.0, 5)
+    b = W.rhs_uniform(n, 6)
+    for t, kw in ((5, dict(reduce=ora.REDUCE_ONCE, t_min=1)), (6, dict(reduce=ora.REDUCE_REPEAT, t_min=1)),
+                  (6, dict(reduce=ora.REDUCE_SCHEDULE, schedule=[2, 4], t_min=1))):
+        part = W.random_partition(n, t, 7)
+        with pytest.raises(ecg.EcgError) as e:
+            _solve(torch, dev, W.dense_to_csr(A), b, part, t, **kw)
+        assert e.value.status == ecg.ECG_EINVAL
+        with pytest.raises(ValueError):
+            ora.flexible_sre_cg2(A, b, part, t, **kw)
+    # 6 -> 3 is allowed when t_min stops the halving there
+    part = W.random_partition(n, 6, 7)
+    rep, _, _ = _solve(torch, dev, W.dense_to_csr(A), b, part, 6, reduce=ora.REDUCE_REPEAT, t_min=3)
+    assert rep["status"] == "ok"
+    op = ecg.Operator.from_csr(p.A)
+    P = ecg.Partition(p.part, p.t)
+    bt = _t(torch, dev, p.b)
+    for bad in (bt.float(), bt[:-1], torch.zeros(2 * p.n, dtype=torch.float64, device=dev)[::2], bt.cpu()):
+        with pytest.raises(ValueError):
+            ecg.solve(op, P, bad, torch.zeros_like(bt), ecg.options(tol=p.tol))

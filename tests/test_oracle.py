@@ -283,6 +283,19 @@ def test_repeated_halving_reaches_t_min():
     assert res.t_final == widths[-1]
 
 
+@pytest.mark.parametrize("t,kw", [(5, dict(reduce=ecg.REDUCE_ONCE)), (6, dict(reduce=ecg.REDUCE_REPEAT)),
+                                  (12, dict(reduce=ecg.REDUCE_SCHEDULE, schedule=[2, 3, 4]))])
+def test_halving_an_odd_width_is_rejected(t, kw):
+    # subdomains merge in pairs (2i, 2i+1; Section 4): an odd width cannot be halved
+    A, b, part = tiny(n=48, t=t, seed=5)
+    with pytest.raises(ValueError):
+        ecg.flexible_sre_cg2(A, b, part, t, t_min=1, **kw)
+    with pytest.raises(ValueError):
+        ecg.flexible_msdo_cg(A, b, part, t, t_min=1, **kw)
+    # a t_min that stops the halving before the odd width is accepted
+    ecg.flexible_sre_cg2(A, b, part, t, t_min=t // 2 if t % 2 == 0 else t, kmax=3, **kw)
+
+
 # ---------------------------------------------------------------- deflation and failures
 def test_zero_subdomain_residual_is_deflated():
     A, b, part = tiny(n=40, t=4, seed=29)
