@@ -224,6 +224,7 @@ class EcgResult:
     blocks: list = field(default_factory=list)
     residuals: list = field(default_factory=list)
     restart_iters: list = field(default_factory=list)
+    candidates: list = field(default_factory=list)  # MSDO-CG: P_k before its A-orthonormalisation
 
     @property
     def mem(self) -> int:
@@ -498,6 +499,8 @@ def flexible_msdo_cg(A, b, part, t, *, x0=None, tol=1e-8, kmax=20000, reduce=RED
             beta = -(V_prev.T @ rr)
             cand = split_term(r, level, t_cur) + P_prev * beta[None, :]
         ref2 = np.einsum("ij,ij->j", cand, cand)  # column norms before CGS2 (deflation reference)
+        if record:
+            res.candidates.append(cand.copy())
         active = blocks if trunc <= 0 else blocks[-trunc:]
         if active:
             cand = a_orthonormalize_against(cand, np.hstack(active), A)
