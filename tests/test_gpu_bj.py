@@ -7,7 +7,7 @@ order in the oracle, a right-looking band sweep on the device) agree only to abo
 kappa(A_g) u in their action, so that comparison allows 8 u max_g kappa(A_g) relative to the
 largest entry (never less than 1e-13); IC(0), computed in the same order on both sides, is
 held to 1e-12.  Preconditioned solves keep the parity bar of the other solver tests
-(iteration and switch counts exactly, iterates to 1e-9 relative).
+(iteration and switch counts exactly, iterates to 1e-10 relative).
 """
 
 import numpy as np
@@ -20,6 +20,14 @@ from oracle import ecg as ora
 from oracle import precond as opre
 
 pytestmark = pytest.mark.gpu
+
+
+def _assert_x_close(x, xo, tol=1e-10):
+    """Solution parity: relative 2-norm error and largest entry error (relative to the largest
+    oracle entry) both within tol."""
+    err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    emax = np.abs(x - xo).max() / np.abs(xo).max()
+    assert err <= tol and emax <= tol, (err, emax)
 
 BJ_IC0, BJ_CHOL, MSDO = 0, 1, 1
 
@@ -129,8 +137,8 @@ def test_chol64_preconditioned_flexible_parity(torch_dev, variant):
     assert rep["status"] == "ok"
     assert rep["iters"] == ref.it and rep["switch_iters"] == ref.switch_iters
     assert rep["vectors_stored"] == ref.mem and rep["deflated_cols"] == ref.deflated
-    assert np.abs(rh - np.array(ref.rho)).max() <= 1e-9 * ref.rho[0]
-    assert np.linalg.norm(x - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
+    assert np.abs(rh - np.array(ref.rho)).max() <= 1e-10 * ref.rho[0]
+    _assert_x_close(x, ref.x)
 
 
 def test_ichol128_preconditioned_parity(torch_dev):
@@ -141,7 +149,7 @@ def test_ichol128_preconditioned_parity(torch_dev):
     ref = ora.flexible_sre_cg2(A, p.b, p.part, p.t, tol=1e-8, precond=pre)
     rep, x, _ = _solve(torch, dev, p, lambda ecg, op: ecg.Precond.bj(op, blocks, BJ_IC0), tol=1e-8)
     assert rep["iters"] == ref.it
-    assert np.linalg.norm(x - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
+    _assert_x_close(x, ref.x)
 
 
 def test_one_block_cholesky_converges_in_one_iteration(torch_dev):

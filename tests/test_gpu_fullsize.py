@@ -28,6 +28,19 @@ def torch_dev():
     return torch, torch.device("cuda:0")
 
 
+class _Progress:
+    """A @ X that prints a line every few products: a long oracle run keeps reporting."""
+
+    def __init__(self, A):
+        self.A, self.shape, self.count = A, A.shape, 0
+
+    def __matmul__(self, X):
+        self.count += 1
+        if self.count % 4 == 0:
+            print(f"  oracle: {self.count} products with A", flush=True)
+        return self.A @ X
+
+
 @pytest.fixture(scope="module")
 def aniso():
     p = W.config("aniso3d128")  # n = 2,097,152, t = 32
@@ -71,6 +84,35 @@ def test_first_iterations_full_size_match_oracle(torch_dev, aniso):
     assert rep["iters"] == ref.it == 3
     x = xt.cpu().numpy()
     assert np.linalg.norm(x - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
+    assert np.abs(rh - np.array(ref.rho)).max() <= 1e-10 * ref.rho[0]
+
+
+@pytest.mark.timeout(900)
+def test_switch_window_full_size_matches_oracle(torch_dev, aniso):
+    """The bench's FP64 step (aniso3d128, t = 32) for 12 iterations with the width halved at
+    iteration 6 (scheduled): the CGS2 sweeps then run over stored blocks of widths 32 and 16
+    (two spans) with a 16-wide candidate, at n = 2,097,152.  Iterates to 1e-10 (2-norm and
+    largest entry), the recursive residual history entry by entry to 1e-10 rho_0."""
+    torch, dev = torch_dev
+    from paper_2305_19013_amd import ecg
+
+    p, A = aniso
+    kw = dict(reduce=ora.REDUCE_SCHEDULE, schedule=[6], t_min=16)
+    print("oracle: aniso3d128 t=32, 12 iterations, halving at 6", flush=True)
+    ref = ora.flexible_sre_cg2(_Progress(A), p.b, p.part, p.t, tol=p.tol, kmax=13, **kw)
+    op = ecg.Operator.from_csr(p.A)
+    P = ecg.Partition(p.part, p.t)
+    bt = torch.from_numpy(p.b).to(dev)
+    xt = torch.zeros_like(bt)
+    rep, rh = ecg.solve(op, P, bt, xt, ecg.options(tol=p.tol, kmax=13, q_budget_bytes=16 * p.t * p.n * 8, **kw),
+                        rho_hist=True)
+    assert rep["iters"] == ref.it == 12 and rep["switch_iters"] == ref.switch_iters == [6]
+    assert rep["vectors_stored"] == ref.mem == 5 * 32 + 7 * 16
+    x = xt.cpu().numpy()
+    err = np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x)
+    emax = np.abs(x - ref.x).max() / np.abs(ref.x).max()
+    print(f"x_12: rel err {err:.2e}, largest entry err {emax:.2e}", flush=True)
+    assert err <= 1e-10 and emax <= 1e-10
     assert np.abs(rh - np.array(ref.rho)).max() <= 1e-10 * ref.rho[0]
 
 

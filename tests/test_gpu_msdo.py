@@ -14,6 +14,14 @@ from oracle import precond as opre
 
 pytestmark = pytest.mark.gpu
 
+
+def _assert_x_close(x, xo, tol=1e-10):
+    """Solution parity: relative 2-norm error and largest entry error (relative to the largest
+    oracle entry) both within tol."""
+    err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    emax = np.abs(x - xo).max() / np.abs(xo).max()
+    assert err <= tol and emax <= tol, (err, emax)
+
 MSDO, MODIFIED = 1, 2
 
 
@@ -94,7 +102,7 @@ def test_msdo_block_jacobi_parity(torch_dev):
     rep, x, rh = _solve(torch, dev, p.A, p.b, p.part, p.t, tol=1e-8, variant=MSDO,
                         M=lambda ecg, op, P: ecg.Precond.bj_ic0(op, P))
     assert rep["iters"] == ref.it and rep["deflated_cols"] == ref.deflated
-    assert np.linalg.norm(x - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
+    _assert_x_close(x, ref.x)
 
 
 def test_msdo_repeated_halving_parity(torch_dev):
@@ -123,7 +131,7 @@ def test_deflation_reference_near_termination(torch_dev, n, t):
     assert rep["status"] == "breakdown"
     assert rep["iters"] == ref.it and rep["deflated_cols"] == ref.deflated
     assert rep["vectors_stored"] == ref.mem <= n
-    assert np.linalg.norm(x - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
+    _assert_x_close(x, ref.x)
 
 
 def test_variant_rejected(torch_dev):
@@ -144,8 +152,8 @@ def test_truncated_msdo_and_modified_msdo_parity(torch_dev):
     ref = ora.flexible_msdo_cg(A, p.b, p.part, p.t, tol=p.tol, trunc=6)
     rep, x, rh = _solve(torch, dev, p.A, p.b, p.part, p.t, tol=p.tol, variant=MSDO, trunc=6)
     assert rep["iters"] == ref.it and rep["trunc_used"] == 6
-    assert np.linalg.norm(x - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
+    _assert_x_close(x, ref.x)
     ref = ora.flexible_sre_cg2(A, p.b, p.part, p.t, tol=p.tol, trunc=2, candidate="modified-msdo")
     rep, x, rh = _solve(torch, dev, p.A, p.b, p.part, p.t, tol=p.tol, variant=MODIFIED, trunc=2)
     assert rep["iters"] == ref.it
-    assert np.linalg.norm(x - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
+    _assert_x_close(x, ref.x)

@@ -16,6 +16,14 @@ from oracle import precond as opre
 pytestmark = pytest.mark.gpu
 
 
+def _assert_x_close(x, xo, tol=1e-10):
+    """Solution parity: relative 2-norm error and largest entry error (relative to the largest
+    oracle entry) both within tol."""
+    err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    emax = np.abs(x - xo).max() / np.abs(xo).max()
+    assert err <= tol and emax <= tol, (err, emax)
+
+
 @pytest.fixture(scope="module")
 def torch_dev():
     import torch
@@ -226,7 +234,7 @@ def test_tiny_dense_termination_and_padding(torch_dev, n, t):
     assert rep["iters"] == ref.it == -(-n // t)
     assert rep["vectors_stored"] == ref.mem == n
     assert rep["deflated_cols"] == ref.deflated
-    assert np.linalg.norm(x - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
+    _assert_x_close(x, ref.x)
 
 
 def test_deflated_zero_subdomain(torch_dev):
@@ -240,7 +248,7 @@ def test_deflated_zero_subdomain(torch_dev):
     rep, x, _ = _solve(torch, dev, W.dense_to_csr(A), b, part, t, tol=1e-10)
     assert ref.widths[0] == 3
     assert rep["iters"] == ref.it and rep["vectors_stored"] == ref.mem and rep["deflated_cols"] == ref.deflated
-    assert np.linalg.norm(x - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
+    _assert_x_close(x, ref.x)
     rep2, _, _ = _solve(torch, dev, W.dense_to_csr(A), b, part, t, tol=1e-10, deflate_tol=-1.0)
     assert rep2["status"] == "breakdown"
 
@@ -260,10 +268,10 @@ def test_q_budget_truncation_parity(torch_dev):
     ref = ora.flexible_sre_cg2(A, p.b, p.part, p.t, tol=p.tol, trunc=6)
     rep, x, _ = _solve(torch, dev, p.A, p.b, p.part, p.t, tol=p.tol, q_budget_bytes=6 * p.n * 8 * 8)
     assert rep["iters"] == ref.it
-    assert np.linalg.norm(x - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
+    _assert_x_close(x, ref.x)
     rep2, x2, _ = _solve(torch, dev, p.A, p.b, p.part, p.t, tol=p.tol, trunc=6)
     assert rep2["iters"] == ref.it
-    assert np.linalg.norm(x2 - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
+    _assert_x_close(x2, ref.x)
 
 
 def test_nonzero_initial_guess(torch_dev):
@@ -293,7 +301,7 @@ def test_block_jacobi_preconditioned_parity(torch_dev):
     rep, _ = ecg.solve(op, P, bt, xt, ecg.options(tol=1e-8, M=M))
     assert rep["iters"] == ref.it
     x = xt.cpu().numpy()
-    assert np.linalg.norm(x - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
+    _assert_x_close(x, ref.x)
 
 
 def test_factor_preconditioned_parity(torch_dev):
@@ -317,7 +325,7 @@ def test_factor_preconditioned_parity(torch_dev):
     rep, x, _ = _solve(torch, dev, p.A, p.b, p.part, p.t, tol=1e-8, M=M, reduce=ora.REDUCE_ONCE,
                        switch_tol=1e-4, t_min=2)
     assert rep["iters"] == ref.it and rep["switch_iters"] == ref.switch_iters
-    assert np.linalg.norm(x - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
+    _assert_x_close(x, ref.x)
 
 
 def test_fp32_refined_reaches_fp64_accuracy(torch_dev):
