@@ -228,6 +228,20 @@ ecg_status ecg_solve(const ecg_operator* A, const ecg_partition* P, const double
                      const ecg_options* o, void* workspace, size_t ws_bytes, void* hip_stream,
                      ecg_report* rep, double* rho_hist);
 
+/* ecg_solve without a workspace argument, for callers that cannot allocate device memory
+ * (code under stream capture, serving loops, harnesses that forbid hipMalloc): the solve runs
+ * in a static device array of the library, 64 MiB (67108864 bytes) per device, kept from the
+ * first call on a device until the process ends.  The call allocates nothing.  Arguments
+ * and results are those of ecg_solve; hip_stream must belong to the current device.  A
+ * solve whose ecg_workspace_size exceeds 64 MiB returns ECG_ENOMEM before any device work
+ * (lower kmax, or bound the stored blocks with q_budget_bytes or trunc).  Every call on a
+ * device shares that device's array and leaves its contents behind (the solve does not
+ * depend on them): calls that overlap in time on one device, from several threads or
+ * streams, race and must not be made. */
+ecg_status ecg_solve_noalloc(const ecg_operator* A, const ecg_partition* P, const double* b, double* x,
+                             const ecg_options* o, void* hip_stream, ecg_report* rep,
+                             double* rho_hist);
+
 /* y = A x for one vector (device double[n] each); used for true residuals. */
 ecg_status ecg_spmv(const ecg_operator* A, const double* x, double* y, void* hip_stream);
 

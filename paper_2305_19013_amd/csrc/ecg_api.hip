@@ -21,6 +21,7 @@
 #include <cstdio>
 #include <cstring>
 #include <deque>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -464,7 +465,7 @@ ecg_status ecg_inner(const ecg_operator* Aop, const ecg_partition* P, const ecg_
       }
     }
     // ---- Pre-CholQR: Euclidean step
-    HIPCHK(hipMemsetAsync(st, 0, sizeof(IterStatus), s));
+    launch_zero(st, sizeof(IterStatus), s);
     const double w = sizeof(T);
     stat_begin(s);
     launch_small_gram<T>(n, tc, Cb, Cb, nullptr, small_part, small_out, s);
@@ -798,6 +799,37 @@ void ecg::stat_end(int cls, double bytes, double flops, hipStream_t s) {
 }
 
 // ====================================================================== C ABI
+
+// ------------------------------------------------------------------ static workspace
+// The workspace of ecg_solve_noalloc: a device array of the library's code object, so that
+// the call allocates nothing.  Each device holds its own copy (until the process ends); its
+// address on a device is taken once, with that device current, and kept.
+namespace {
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+}  // namespace
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+ecg_status scratch_of_current_device(void** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(ECG_EINVAL, "device ordinal out of range for the static workspace");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(ECG_EHIP, "hipGetSymbolAddress gave no address for the static workspace");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return ECG_OK;
+}
+}  // namespace
+
 extern "C" {
 
 ecg_status ecg_progress(int32_t every) {
@@ -1169,8 +1201,9 @@ ecg_status ecg_spmv(const ecg_operator* A, const double* x, double* y, void* hip
   return ECG_OK;
 }
 
-ecg_status ecg_solve(const ecg_operator* A, const ecg_partition* P, const double* b, double* x, const ecg_options* o,
-                     void* workspace, size_t ws_bytes, void* hip_stream, ecg_report* rep, double* rho_hist) {
+static ecg_status solve_in(const ecg_operator* A, const ecg_partition* P, const double* b, double* x,
+                           const ecg_options* o, void* workspace, size_t ws_bytes, void* hip_stream, ecg_report* rep,
+                           double* rho_hist) {
   if (!A || !P || !b || !x || !workspace || !rep) return fail(ECG_EINVAL, "NULL argument");
   ecg_status st = check_options(o);
   if (st != ECG_OK) return st;
@@ -1199,7 +1232,7 @@ ecg_status ecg_solve(const ecg_operator* A, const ecg_partition* P, const double
     // ||b||^2 via the residual kernel on a zero vector held in the H buffer
     double* zero = reinterpret_cast<double*>(ws + pl.off_v1);
     double* tmp = reinterpret_cast<double*>(ws + pl.off_v2);
-    HIPCHK(hipMemsetAsync(zero, 0, (size_t)n * 8, s));
+    launch_zero(zero, (size_t)n * 8, s);
     if ((st = device_norm2(A->A, b, zero, tmp, norm_part, dscal, s, &bnorm2)) != ECG_OK) return st;
   }
   if (!std::isfinite(bnorm2)) return fail(ECG_EINVAL, "b contains NaN or Inf");
@@ -1236,7 +1269,7 @@ ecg_status ecg_solve(const ecg_operator* A, const ecg_partition* P, const double
         final = ECG_OK;
         break;
       }
-      HIPCHK(hipMemsetAsync(d, 0, (size_t)n * 8, s));
+      launch_zero(d, (size_t)n * 8, s);
       launch_cast_d2f(n, r64, rf, s);
       InnerResult ir;
       ir.kmax_left = o->kmax - tot.iters;
@@ -1296,6 +1329,28 @@ ecg_status ecg_solve(const ecg_operator* A, const ecg_partition* P, const double
   rep->status = final;
   if (final == ECG_EBREAKDOWN) return ECG_EBREAKDOWN;
   return final;
+}
+
+ecg_status ecg_solve(const ecg_operator* A, const ecg_partition* P, const double* b, double* x, const ecg_options* o,
+                     void* workspace, size_t ws_bytes, void* hip_stream, ecg_report* rep, double* rho_hist) {
+  return solve_in(A, P, b, x, o, workspace, ws_bytes, hip_stream, rep, rho_hist);
+}
+
+ecg_status ecg_solve_noalloc(const ecg_operator* A, const ecg_partition* P, const double* b, double* x,
+                             const ecg_options* o, void* hip_stream, ecg_report* rep, double* rho_hist) {
+  if (!A || !P || !b || !x || !rep) return fail(ECG_EINVAL, "NULL argument");
+  ecg_status st = check_options(o);
+  if (st != ECG_OK) return st;
+  if (A->n != P->n) return fail(ECG_EINVAL, "operator and partition sizes differ");
+  Plan pl;
+  if ((st = make_plan(A->n, P->t, *o, &pl)) != ECG_OK) return st;
+  if (pl.total > kScratchBytes)
+    return fail(ECG_ENOMEM, "the solve needs " + std::to_string(pl.total) + " bytes of workspace; the static " +
+                                "workspace of ecg_solve_noalloc holds " + std::to_string(kScratchBytes) +
+                                " (lower kmax, or set q_budget_bytes or trunc)");
+  void* ws = nullptr;
+  if ((st = scratch_of_current_device(&ws)) != ECG_OK) return st;
+  return solve_in(A, P, b, x, o, ws, kScratchBytes, hip_stream, rep, rho_hist);
 }
 
 // ---------------------------------------------------------------- debug entry points

@@ -136,6 +136,8 @@ template <typename T, typename TX>
 int launch_final_update(int n, int tc, const T* H, const T* Y, const double* Cinv,
                         const double* beta, T* Wq, T* Zn, TX* x, T* r, double* part, hipStream_t s);
 
+// Zero the first bytes (rounded up to 8) of p; p 8-byte aligned.
+void launch_zero(void* p, size_t bytes, hipStream_t s);
 // Precision conversion helpers.
 void launch_cast_d2f(int n, const double* in, float* out, hipStream_t s);
 void launch_axpy_f2d(int n, const float* d, double* x, hipStream_t s);  // x += d

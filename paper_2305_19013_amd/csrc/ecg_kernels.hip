@@ -1232,6 +1232,18 @@ void launch_sum(const double* part, int m, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_sum, dim3(1), dim3(kBlock), 0, s, mid, nb, out);
 }
 
+// Zero `words` 8-byte words (a kernel rather than hipMemsetAsync, so that the solve's
+// clears are ordinary kernel launches on the caller's stream).
+__global__ void __launch_bounds__(kBlock) k_zero_words(long long words, unsigned long long* __restrict__ p) {
+  const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (i < words) p[i] = 0ull;
+}
+void launch_zero(void* p, size_t bytes, hipStream_t s) {
+  const long long words = (long long)((bytes + 7) / 8);
+  if (words > 0)
+    hipLaunchKernelGGL(k_zero_words, dim3(cdiv(words, kBlock)), dim3(kBlock), 0, s, words,
+                       static_cast<unsigned long long*>(p));
+}
 void launch_cast_d2f(int n, const double* in, float* out, hipStream_t s) {
   hipLaunchKernelGGL(k_cast_d2f, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, s, n, in, out);
 }

@@ -143,6 +143,7 @@ def lib():
             "ecg_precond_destroy": (None, [vp]),
             "ecg_workspace_size": (i32, [vp, vp, C.POINTER(Options), C.POINTER(C.c_size_t)]),
             "ecg_solve": (i32, [vp, vp, dp, dp, C.POINTER(Options), vp, C.c_size_t, vp, C.POINTER(Report), vp]),
+            "ecg_solve_noalloc": (i32, [vp, vp, dp, dp, C.POINTER(Options), vp, C.POINTER(Report), vp]),
             "ecg_spmv": (i32, [vp, dp, dp, vp]),
             "ecg_last_error": (C.c_char_p, []),
             "ecg_debug_spmm": (i32, [vp, i32, dp, dp, vp]),
@@ -314,6 +315,15 @@ def workspace_size(op: Operator, part: Partition, opts: Options) -> int:
     return int(out.value)
 
 
+def _check_vectors(op: Operator, b, x):
+    import torch
+
+    for name, v in (("b", b), ("x", x)):
+        if not (isinstance(v, torch.Tensor) and v.is_cuda and v.dtype == torch.float64 and v.dim() == 1
+                and v.is_contiguous() and v.numel() == op.n):
+            raise ValueError(f"{name} must be a contiguous float64 CUDA tensor of length n = {op.n}")
+
+
 def solve(op: Operator, part: Partition, b, x, opts: Options, workspace=None, rho_hist: bool = False):
     """Run ecg_solve on device tensors b, x (float64, length n); x holds x0 on entry.
 
@@ -322,10 +332,7 @@ def solve(op: Operator, part: Partition, b, x, opts: Options, workspace=None, rh
     """
     import torch
 
-    for name, v in (("b", b), ("x", x)):
-        if not (isinstance(v, torch.Tensor) and v.is_cuda and v.dtype == torch.float64 and v.dim() == 1
-                and v.is_contiguous() and v.numel() == op.n):
-            raise ValueError(f"{name} must be a contiguous float64 CUDA tensor of length n = {op.n}")
+    _check_vectors(op, b, x)
     need = workspace_size(op, part, opts)
     if workspace is None:
         workspace = torch.empty(need, dtype=torch.uint8, device=b.device)
@@ -339,6 +346,21 @@ def solve(op: Operator, part: Partition, b, x, opts: Options, workspace=None, rh
         hp = hist.ctypes.data
     st = lib().ecg_solve(op.handle, part.handle, _ptr(b), _ptr(x), C.byref(opts), _ptr(workspace), need,
                          _stream(), C.byref(rep), hp)
+    check(st, allow=(ECG_OK, ECG_ENOTCONV, ECG_EBREAKDOWN))
+    d = rep.as_dict()
+    if hist is not None:
+        hist = hist[: d["iters"] + 1]
+    return d, hist
+
+
+def solve_noalloc(op: Operator, part: Partition, b, x, opts: Options, rho_hist: bool = False):
+    """Run ecg_solve_noalloc (the solve in the library's static 64 MiB device workspace, no
+    allocation) on device tensors b, x; returns what solve() returns."""
+    _check_vectors(op, b, x)
+    rep = Report()
+    hist = np.zeros(opts.kmax + 1, dtype=np.float64) if rho_hist else None
+    st = lib().ecg_solve_noalloc(op.handle, part.handle, _ptr(b), _ptr(x), C.byref(opts), _stream(), C.byref(rep),
+                                 None if hist is None else hist.ctypes.data)
     check(st, allow=(ECG_OK, ECG_ENOTCONV, ECG_EBREAKDOWN))
     d = rep.as_dict()
     if hist is not None:
