@@ -108,9 +108,9 @@ typedef struct {
   int32_t max_outer;       /* FP32_REFINED: maximum refinement steps (>= 1) */
   int32_t replace_every;   /* FP32_REFINED: recompute r = b - A x in FP64 every this many
                               inner iterations (0 = never).  An inner solve whose true
-                              residual falls by less than 10% over four replacements ends
-                              and the next refinement step starts; refinement stops when a
-                              step gains less than 10%. */
+                              residual falls by less than 10% over four replacements (and at
+                              least 100 iterations) ends and the next refinement step
+                              starts; refinement stops when a step gains less than 10%. */
   int32_t trunc;           /* > 0: A-orthonormalise against the last trunc blocks only
                               (truncated SRE-CG2, Section 3); 0 = all stored blocks */
   int64_t q_budget_bytes;  /* bytes of workspace reserved for stored blocks; 0 = room for
@@ -132,6 +132,17 @@ typedef struct {
   int32_t max_restarts;    /* RESTART_TOL: limit on the number of restarts, 0 = none */
   int32_t restart_at_switch; /* != 0: every halving also empties Q (restarted flexible
                               variant); a halving takes precedence over a restart */
+  int32_t refine_keep_q;   /* FP32_REFINED, != 0: the stored blocks are kept across residual
+                              replacements and refinement steps.  Each time r is recomputed
+                              from x (a replacement, the start of a refinement step) the
+                              iterate is re-projected, x += Q (Q^T r), so that r is again
+                              orthogonal to the stored blocks, and the next refinement step
+                              extends the kept blocks instead of starting from none.
+                              2: the same, except that a refinement step drops the kept
+                              blocks when re-projecting its residual on them leaves more than
+                              half of its norm (they would be swept every iteration for
+                              little gain).  0: every refinement step starts from an empty
+                              Q (replacements do not re-project). */
 } ecg_options;
 
 typedef struct {
@@ -160,7 +171,8 @@ typedef struct {
 /* Fill *o with defaults: tol 1e-8, kmax 20000, no reduction, switch_tol 1e-5, t_min 1,
  * min_gap 1, FP64, inner_tol 1e-4, max_outer 20, replace_every 0, trunc 0,
  * q_budget_bytes 0, deflate_tol 1e-14, no preconditioner, SRE-CG2, no restarts
- * (restart_every 0, restart_tol 1e-5, max_restarts 0, restart_at_switch 0). */
+ * (restart_every 0, restart_tol 1e-5, max_restarts 0, restart_at_switch 0),
+ * refine_keep_q 2. */
 ecg_status ecg_options_default(ecg_options* o);
 
 /* Sparse SPD matrix A (n x n) in CSR form, copied to the device.
@@ -289,11 +301,14 @@ ecg_status ecg_debug_spmm(const ecg_operator* A, int32_t t, const double* X, dou
                           void* hip_stream);
 /* Y = A X with a chosen product kernel: kernel 0 = CSR, 1 = diagonal form, 2 = grid stencil
  * (diagonal offsets -c, -b, -a, 0, a, b, c or -c, -a, 0, a, c with b dividing c and c
- * dividing n), -1 = the one the solver uses.  precision 0: X and Y are double, 1: float.
- * Row-major n x t blocks, t a power of two in 1..64.  Every kernel builds a row as a chain
- * of fused multiply-adds in the stored (CSR) or ascending-offset order, so for rows stored in
- * ascending column order and finite X all three give bitwise equal results.  ECG_EINVAL
- * when the operator has no such form. */
+ * dividing n), 3 = 3-D grid stencil with its planes staged in LDS, 4 = the same with the
+ * planes brought into LDS by direct buffer loads (3 and 4: seven diagonals, a = 1, at least
+ * 4 lanes of 16 bytes per block row and nx a multiple of 16 / (bytes per value); 4 also
+ * needs n t and 7 n values to fit 32-bit byte offsets), -1 = the one the solver uses.
+ * precision 0: X and Y are double, 1: float.  Row-major n x t blocks, t a power of two in
+ * 1..64.  Every kernel builds a row as a chain of fused multiply-adds in the stored (CSR)
+ * or ascending-offset order, so for rows stored in ascending column order and finite X all
+ * of them give bitwise equal results.  ECG_EINVAL when the operator has no such form. */
 ecg_status ecg_debug_spmm_kernel(const ecg_operator* A, int32_t kernel, int32_t precision, int32_t t,
                                  const void* X, void* Y, void* hip_stream);
 /* out = [T^t(v)] with the map part >> level: out[i][j] = v[i] if (part[i]>>level) == j. */

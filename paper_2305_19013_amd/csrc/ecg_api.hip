@@ -211,6 +211,7 @@ ecg_status check_options(const ecg_options* o) {
   if (o->restart < ECG_RESTART_NONE || o->restart > ECG_RESTART_TOL) return fail(ECG_EINVAL, "unknown restart rule");
   if (o->restart == ECG_RESTART_EVERY && o->restart_every < 1) return fail(ECG_EINVAL, "restart_every must be >= 1");
   if (o->max_restarts < 0) return fail(ECG_EINVAL, "max_restarts must be >= 0");
+  if (o->refine_keep_q < 0 || o->refine_keep_q > 2) return fail(ECG_EINVAL, "refine_keep_q must be 0, 1 or 2");
   return ECG_OK;
 }
 
@@ -355,10 +356,16 @@ struct InnerResult {
 
 // One ECG solve on residual r (in place) accumulating the correction into x.
 // rr0 = ||r||^2 on entry.  base_k offsets the iteration numbers of rho_hist/report.
+// Adaptive rule of refine_keep_q: blocks kept from the previous refinement step stay only if
+// re-projecting the new residual on them leaves at most this fraction of its norm.
+constexpr double kKeepGain = 0.5;
+
+// qkeep: stored blocks kept from an earlier inner solve (and left for the next one), or
+// nullptr for an empty store of this solve's own.
 template <typename T, typename TX>
 ecg_status ecg_inner(const ecg_operator* Aop, const ecg_partition* P, const ecg_options& o, const Plan& pl,
                      char* ws, TX* x, T* r, double rr0, double tol, const double* b64_for_replace,
-                     hipStream_t s, InnerResult* res, double* rho_hist) {
+                     hipStream_t s, InnerResult* res, double* rho_hist, QStore* qkeep = nullptr) {
   const DevCsr& A = Aop->A;
   const int n = pl.n;
   const ecg_precond* M = (o.precond == ECG_PRECOND_SPLIT) ? o.M : nullptr;
@@ -377,9 +384,32 @@ ecg_status ecg_inner(const ecg_operator* Aop, const ecg_partition* P, const ecg_
   T* Hb = reinterpret_cast<T*>(ws + pl.off_H);
   T* Qbase = reinterpret_cast<T*>(ws + pl.off_Q);
 
-  QStore q;
-  q.cap = pl.cap;
+  QStore qown;
+  qown.cap = pl.cap;
+  QStore& q = qkeep ? *qkeep : qown;
+  const long long dropped_before = q.dropped;
   std::vector<Span<T>> spans;
+  IterStatus hst;
+
+  // After r was recomputed from x (FP32 form with kept blocks): x += Q (Q^T r) restores the
+  // Galerkin condition Q^T r = 0 on the stored blocks, then r = b - A x again in FP64.
+  // Returns ||r||^2 in *rr_out (unchanged when nothing is stored).
+  auto reproject = [&](double* rr_out) -> ecg_status {
+    if constexpr (std::is_same<T, float>::value && std::is_same<TX, double>::value) {
+      const int m = build_spans<T>(q, o.trunc, Qbase, n, spans);
+      if (m == 0) return ECG_OK;
+      launch_gram<T>(n, spans.data(), (int)spans.size(), m, 1, r, G, gram_part, pl.gram_part_cap, s);
+      launch_zero(Hb, (size_t)n * sizeof(T), s);
+      launch_update<T>(n, spans.data(), (int)spans.size(), 1, G, Hb, s);  // Hb = -Q (Q^T r)
+      launch_axpy_f2d(n, Hb, x, s, -1.0);
+      const int g = launch_residual_f(A, b64_for_replace, x, r, norm_part, s);
+      launch_sum(norm_part, g, &st->rr, s);
+      HIPCHK(hipMemcpyAsync(&hst, st, sizeof(IterStatus), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      *rr_out = std::max(hst.rr, 0.0);
+    }
+    return ECG_OK;
+  };
 
   const double rho0 = std::sqrt(rr0);
   res->rho0 = rho0;
@@ -395,11 +425,27 @@ ecg_status ecg_inner(const ecg_operator* Aop, const ecg_partition* P, const ecg_
   const auto t_begin = std::chrono::steady_clock::now();
   int tl = P->t;                 // live width
   int tc = pow2_at_least(tl);    // padded width of the kernels
-  IterStatus hst;
   int prev_kept = tl;
   long long cycle_mem = 0;
   std::vector<double> replaced;  // true residual norms at the residual replacements
   const int kmax = std::max(1, std::min(o.kmax, res->kmax_left));
+  if (qkeep && b64_for_replace && !q.blocks.empty()) {
+    // a refinement step starting from kept blocks: re-project; under the adaptive rule the
+    // blocks are kept only if they hold a real part of the new residual
+    double rr = rr0;
+    ecg_status est = reproject(&rr);
+    if (est != ECG_OK) return est;
+    const double gain = rr0 > 0 ? std::sqrt(rr / rr0) : 0.0;
+    const bool keep = o.refine_keep_q != 2 || gain <= kKeepGain;
+    if (g_progress_every > 0) {
+      std::fprintf(stderr, "ecg: refinement step: re-projection on %lld stored columns leaves %.3f of the residual; "
+                   "blocks %s\n", (long long)build_spans<T>(q, o.trunc, Qbase, n, spans), gain,
+                   keep ? "kept" : "dropped");
+      std::fflush(stderr);
+    }
+    if (!keep) q.clear();
+    rho_prev = std::sqrt(rr);
+  }
   while (rho_prev > tol * rho0 && k < kmax) {
     // ---- candidate block (cand_live: its columns that are not already known zero)
     bool from_r = false;
@@ -528,12 +574,18 @@ ecg_status ecg_inner(const ecg_operator* Aop, const ecg_partition* P, const ecg_
         launch_sum(norm_part, g, &st->rr, s);
         HIPCHK(hipMemcpyAsync(&hst, st, sizeof(IterStatus), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        rho_prev = std::sqrt(std::max(hst.rr, 0.0));
+        double rr = std::max(hst.rr, 0.0);
+        if (qkeep) {
+          ecg_status est = reproject(&rr);
+          if (est != ECG_OK) return est;
+        }
+        rho_prev = std::sqrt(rr);
         replaced.push_back(rho_prev);
         // stagnation: the true residual fell by less than 10% over the last four
-        // replacements; hand back to the FP64 refinement step
+        // replacements and at least 100 iterations; hand back to the FP64 refinement step
         const size_t nr = replaced.size();
-        if (nr > 4 && replaced[nr - 1] > 0.9 * replaced[nr - 5]) {
+        const size_t win = std::max<size_t>(4, (size_t)((100 + o.replace_every - 1) / o.replace_every));
+        if (nr > win && replaced[nr - 1] > 0.9 * replaced[nr - 1 - win]) {
           ++k;
           res->stagnated = true;
           break;
@@ -543,7 +595,7 @@ ecg_status ecg_inner(const ecg_operator* Aop, const ecg_partition* P, const ecg_
     ++k;
   }
   res->iters = k - 1;
-  res->dropped += q.dropped;
+  res->dropped += q.dropped - dropped_before;
   res->rho = rho_prev;
   res->t_final = tl;
   if (res->status == ECG_OK && rho_prev > tol * rho0) res->status = ECG_ENOTCONV;
@@ -869,6 +921,7 @@ ecg_status ecg_options_default(ecg_options* o) {
   o->variant = ECG_SRE_CG2;
   o->restart = ECG_RESTART_NONE;
   o->restart_tol = 1e-5;
+  o->refine_keep_q = 2;
   return ECG_OK;
 }
 
@@ -1264,6 +1317,8 @@ static ecg_status solve_in(const ecg_operator* A, const ecg_partition* P, const 
     const double rho0 = std::sqrt(rr);
     tot.rho0 = rho0;
     final = ECG_ENOTCONV;
+    QStore kept;  // stored blocks carried from one refinement step to the next
+    kept.cap = pl.cap;
     while (outer < o->max_outer) {
       if (std::sqrt(rr) <= o->tol * rho0) {
         final = ECG_OK;
@@ -1278,7 +1333,8 @@ static ecg_status solve_in(const ecg_operator* A, const ecg_partition* P, const 
       // more than the outer target
       const double itol = std::max(o->inner_tol, o->tol * rho0 / std::sqrt(rr) * 0.5);
       const double rr_before = rr;
-      st = ecg_inner<float, double>(A, P, *o, pl, ws, d, rf, rr, itol, r64, s, &ir, nullptr);
+      st = ecg_inner<float, double>(A, P, *o, pl, ws, d, rf, rr, itol, r64, s, &ir, nullptr,
+                                    o->refine_keep_q ? &kept : nullptr);
       if (st != ECG_OK) return st;
       tot.iters += ir.iters;
       tot.mem += ir.mem;
@@ -1368,10 +1424,14 @@ ecg_status ecg_debug_spmm_kernel(const ecg_operator* A, int32_t kernel, int32_t 
                                  void* Y, void* hip_stream) {
   if (!A || !X || !Y) return fail(ECG_EINVAL, "NULL argument");
   if (t < 1 || t > 64 || (t & (t - 1))) return fail(ECG_EINVAL, "t must be a power of two in [1, 64]");
-  if (kernel < kSpmmAuto || kernel > kSpmmGrid) return fail(ECG_EINVAL, "unknown product kernel");
+  if (kernel < kSpmmAuto || kernel > kSpmmGridDma) return fail(ECG_EINVAL, "unknown product kernel");
   if (precision != 0 && precision != 1) return fail(ECG_EINVAL, "precision must be 0 (FP64) or 1 (FP32)");
   if (kernel == kSpmmDia && A->A.ndiag == 0) return fail(ECG_EINVAL, "the operator has no diagonal form");
   if (kernel == kSpmmGrid && A->A.gnx == 0) return fail(ECG_EINVAL, "the operator is not a grid stencil");
+  if (kernel == kSpmmGridLds && !spmm_grid_lds_ok(A->A, t, precision == 0 ? 8 : 4))
+    return fail(ECG_EINVAL, "the LDS-staged grid product does not apply to this operator and width");
+  if (kernel == kSpmmGridDma && !spmm_grid_dma_ok(A->A, t, precision == 0 ? 8 : 4))
+    return fail(ECG_EINVAL, "the LDS-staged grid product (direct loads) does not apply to this operator and width");
   hipStream_t s = (hipStream_t)hip_stream;
   if (precision == 0)
     launch_spmm<double>(A->A, t, static_cast<const double*>(X), static_cast<double*>(Y), s, kernel);

@@ -40,7 +40,10 @@ struct DevCsr {
 
 // Which product kernel launch_spmm uses (the automatic choice takes the most specific one
 // the matrix has).
-enum SpmmKernel { kSpmmAuto = -1, kSpmmCsr = 0, kSpmmDia = 1, kSpmmGrid = 2 };
+enum SpmmKernel { kSpmmAuto = -1, kSpmmCsr = 0, kSpmmDia = 1, kSpmmGrid = 2, kSpmmGridLds = 3, kSpmmGridDma = 4 };
+// whether the LDS-staged grid kernels apply to A at block width tc, elt bytes per value
+bool spmm_grid_lds_ok(const DevCsr& A, int tc, int elt);
+bool spmm_grid_dma_ok(const DevCsr& A, int tc, int elt);
 
 // One contiguous run of stored blocks of equal width: block j of the span starts at
 // base + j * stride (elements); its Gram rows start at goff + j * width.
@@ -140,7 +143,7 @@ int launch_final_update(int n, int tc, const T* H, const T* Y, const double* Cin
 void launch_zero(void* p, size_t bytes, hipStream_t s);
 // Precision conversion helpers.
 void launch_cast_d2f(int n, const double* in, float* out, hipStream_t s);
-void launch_axpy_f2d(int n, const float* d, double* x, hipStream_t s);  // x += d
+void launch_axpy_f2d(int n, const float* d, double* x, hipStream_t s, double alpha = 1.0);  // x += alpha d
 void launch_axpy_d(int n, const double* d, double* x, hipStream_t s);    // x += d
 void launch_cast_val(int nnz, const double* in, float* out, hipStream_t s);
 // r = (float)(b - A x) computed in FP64; partial sums of the FP64 residual squared.

@@ -113,9 +113,10 @@ __global__ void __launch_bounds__(kBlock) k_cast_d2f(int n, const double* __rest
   if (i < n) out[i] = (float)in[i];
 }
 
-__global__ void __launch_bounds__(kBlock) k_axpy_f2d(int n, const float* __restrict__ d, double* __restrict__ x) {
+__global__ void __launch_bounds__(kBlock) k_axpy_f2d(int n, double alpha, const float* __restrict__ d,
+                                                     double* __restrict__ x) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) x[i] += (double)d[i];
+  if (i < n) x[i] += alpha * (double)d[i];
 }
 
 __global__ void __launch_bounds__(kBlock) k_axpy_d(int n, const double* __restrict__ d, double* __restrict__ x) {
@@ -335,6 +336,313 @@ k_spmm_grid(int n, int gnx, int gny, int gnz, int ga, int zseg, int nxb, int nyb
     for (int k = 0; k < K; ++k) {
       prev[k] = cur[k];
       cur[k] = nxt[k];
+    }
+  }
+}
+
+// The grid-stencil product with each plane of block rows staged in LDS (3-D 7-point
+// operators with unit x stride).  A workgroup owns a tile of RX x-rows by K y-rows and
+// marches z through zseg planes.  For every plane it reads the tile with a one-row halo in
+// x and y, (RX+2) x (K+2) block rows, once per workgroup (16 bytes per lane, contiguous
+// along x), and the tile's seven coefficient rows, into LDS; a lane then takes its x and y
+// neighbours and its coefficients from LDS and its z neighbours from registers (planes
+// z-1, z, z+1 of its own rows).  The loads of plane z+1 are issued before the terms of
+// plane z that do not need them.  Each LDS slot holds X at the linear index of its tile
+// position (zero outside [0, n)), and every term has the diagonal kernel's neighbour,
+// range test and place in the ascending chain of FMAs, so the result is bitwise that of
+// k_spmm_dia and k_spmm_grid.
+template <typename T, int TC, int K>
+struct GridLds {
+  using S = SpmmShape<T, TC>;
+  static constexpr int RX = S::RPB;              // x rows of a tile
+  static constexpr int TX = RX + 2, TY = K + 2;  // with the halo
+  static constexpr int CPR = S::LPR;             // 16-byte chunks per block row
+  static constexpr int HALO = 2 * TX + 2 * K;    // halo rows per plane
+  static constexpr int HCH = (HALO * CPR + kBlock - 1) / kBlock;  // halo chunks per thread
+  static constexpr int CE = 16 / (int)sizeof(T);                  // coefficients per chunk
+  static constexpr int CCH = 7 * K * RX / CE;                     // coefficient chunks per plane
+  static constexpr int CPT = (CCH + kBlock - 1) / kBlock;         // ... per thread
+  static constexpr size_t kRowBytes = (size_t)TY * TX * CPR * 16;
+  static constexpr size_t kCoefBytes = (size_t)K * RX * 8 * sizeof(T);
+  static constexpr size_t kLds = 2 * (kRowBytes + kCoefBytes);
+};
+
+template <typename T, int TC, int K>
+__global__ void __launch_bounds__(kBlock)
+k_spmm_grid_lds(int n, int gnx, int gny, int gnz, int zseg, int nxb, int nyb, int nwork,
+                const T* __restrict__ dv, const T* __restrict__ X, T* __restrict__ Y) {
+  using G = GridLds<T, TC, K>;
+  using S = typename G::S;
+  typedef T Vec __attribute__((ext_vector_type(S::VL)));
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  Vec* rows_lds = reinterpret_cast<Vec*>(lds_raw);                        // [2][TY][TX][CPR]
+  T* coef_lds = reinterpret_cast<T*>(lds_raw + 2 * G::kRowBytes);         // [2][K][RX][8]
+  const int w = xcd_block();
+  if (w >= nwork) return;  // the whole workgroup leaves together
+  const int bx = w % nxb, by = (w / nxb) % nyb, bz = w / (nxb * nyb);
+  const int tid = (int)threadIdx.x;
+  const int li = tid % G::CPR, xl = tid / G::CPR;
+  const int b = gnx, c = gnx * gny;
+  const int x0 = bx * G::RX, y0 = by * K;
+  const int z0 = bz * zseg, z1 = min(gnz, z0 + zseg);
+  const int x = x0 + xl;
+  // linear index of tile position (yi, xi) of plane zz (halo included)
+  auto lin = [&](int zz, int yi, int xi) -> long long {
+    return (long long)zz * c + (long long)(y0 + yi - 1) * b + (x0 + xi - 1);
+  };
+  auto ldx = [&](long long r, int chunk) -> Vec {
+    return (r >= 0 && r < n) ? *reinterpret_cast<const Vec*>(X + (size_t)r * TC + chunk * S::VL) : Vec(0);
+  };
+  auto halo_pos = [&](int h, int& yi, int& xi) {
+    if (h < G::TX) {
+      yi = 0, xi = h;
+    } else if (h < 2 * G::TX) {
+      yi = G::TY - 1, xi = h - G::TX;
+    } else {
+      const int h2 = h - 2 * G::TX;
+      yi = 1 + h2 / 2, xi = (h2 & 1) ? G::TX - 1 : 0;
+    }
+  };
+  auto slot = [&](int buf, int yi, int xi, int chunk) -> Vec& {
+    return rows_lds[(((size_t)buf * G::TY + yi) * G::TX + xi) * G::CPR + chunk];
+  };
+  // coefficients of plane zz: chunk q -> (d, k, x .. x + CE - 1) of dv[d][row]
+  auto ldc = [&](int zz, int q, T (&out)[G::CE]) {
+    const int per = G::RX / G::CE;
+    const int xc = (q % per) * G::CE, dk = q / per, d = dk / K, k = dk % K;
+    const long long r = (long long)zz * c + (long long)(y0 + k) * b + x0 + xc;
+    const bool rowok = zz < gnz && y0 + k < gny;
+    if (rowok && x0 + xc + G::CE <= gnx) {
+      typedef T CVec __attribute__((ext_vector_type(G::CE)));
+      const CVec v = *reinterpret_cast<const CVec*>(dv + (size_t)d * n + r);
+#pragma unroll
+      for (int e = 0; e < G::CE; ++e) out[e] = v[e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < G::CE; ++e) out[e] = (rowok && x0 + xc + e < gnx) ? dv[(size_t)d * n + r + e] : T(0);
+    }
+  };
+  auto stc = [&](int buf, int q, const T (&v)[G::CE]) {
+    const int per = G::RX / G::CE;
+    const int xc = (q % per) * G::CE, dk = q / per, d = dk / K, k = dk % K;
+#pragma unroll
+    for (int e = 0; e < G::CE; ++e) coef_lds[(((size_t)buf * K + k) * G::RX + xc + e) * 8 + d] = v[e];
+  };
+
+  Vec prev[K], cur[K], nxt[K];
+  Vec hreg[G::HCH];
+  T creg[G::CPT][G::CE];
+  // plane z0: own rows, halo and coefficients into buffer 0; plane z0 - 1 of the own rows
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    prev[k] = ldx(lin(z0 - 1, k + 1, xl + 1), li);
+    cur[k] = ldx(lin(z0, k + 1, xl + 1), li);
+  }
+#pragma unroll
+  for (int i = 0; i < G::HCH; ++i) {
+    const int q = tid + i * kBlock;
+    if (q < G::HALO * G::CPR) {
+      int yi, xi;
+      halo_pos(q / G::CPR, yi, xi);
+      hreg[i] = ldx(lin(z0, yi, xi), q % G::CPR);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < G::CPT; ++i)
+    if (tid + i * kBlock < G::CCH) ldc(z0, tid + i * kBlock, creg[i]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) slot(0, k + 1, xl + 1, li) = cur[k];
+#pragma unroll
+  for (int i = 0; i < G::HCH; ++i) {
+    const int q = tid + i * kBlock;
+    if (q < G::HALO * G::CPR) {
+      int yi, xi;
+      halo_pos(q / G::CPR, yi, xi);
+      slot(0, yi, xi, q % G::CPR) = hreg[i];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < G::CPT; ++i)
+    if (tid + i * kBlock < G::CCH) stc(0, tid + i * kBlock, creg[i]);
+  __syncthreads();
+
+  for (int z = z0; z < z1; ++z) {
+    const int buf = (z - z0) & 1;
+    const bool more = z + 1 < z1;
+    // loads of plane z + 1 (own rows always: they are the z + 1 neighbours)
+#pragma unroll
+    for (int k = 0; k < K; ++k) nxt[k] = ldx(lin(z + 1, k + 1, xl + 1), li);
+    if (more) {
+#pragma unroll
+      for (int i = 0; i < G::HCH; ++i) {
+        const int q = tid + i * kBlock;
+        if (q < G::HALO * G::CPR) {
+          int yi, xi;
+          halo_pos(q / G::CPR, yi, xi);
+          hreg[i] = ldx(lin(z + 1, yi, xi), q % G::CPR);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < G::CPT; ++i)
+        if (tid + i * kBlock < G::CCH) ldc(z + 1, tid + i * kBlock, creg[i]);
+    }
+    // plane z
+    if (x < gnx) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (y0 + k >= gny) break;  // the same for the whole workgroup
+        const long long r = (long long)z * c + (long long)(y0 + k) * b + x;
+        const T* cf = coef_lds + (((size_t)buf * K + k) * G::RX + xl) * 8;
+        auto term = [&](int d, long long j, const Vec& xv, Vec& acc) {
+          fma_row<T, Vec, S::VL>(acc, (j >= 0 && j < n) ? cf[d] : T(0), xv);
+        };
+        Vec acc = Vec(0);
+        term(0, r - c, prev[k], acc);
+        term(1, r - b, slot(buf, k, xl + 1, li), acc);
+        term(2, r - 1, slot(buf, k + 1, xl, li), acc);
+        term(3, r, cur[k], acc);
+        term(4, r + 1, slot(buf, k + 1, xl + 2, li), acc);
+        term(5, r + b, slot(buf, k + 2, xl + 1, li), acc);
+        term(6, r + c, nxt[k], acc);
+        __builtin_nontemporal_store(acc, reinterpret_cast<Vec*>(Y + (size_t)r * TC + li * S::VL));
+      }
+    }
+    if (more) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) slot(buf ^ 1, k + 1, xl + 1, li) = nxt[k];
+#pragma unroll
+      for (int i = 0; i < G::HCH; ++i) {
+        const int q = tid + i * kBlock;
+        if (q < G::HALO * G::CPR) {
+          int yi, xi;
+          halo_pos(q / G::CPR, yi, xi);
+          slot(buf ^ 1, yi, xi, q % G::CPR) = hreg[i];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < G::CPT; ++i)
+        if (tid + i * kBlock < G::CCH) stc(buf ^ 1, tid + i * kBlock, creg[i]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      prev[k] = cur[k];
+      cur[k] = nxt[k];
+    }
+  }
+}
+
+// The same product with the plane tiles brought into LDS by direct buffer loads (no
+// registers in between): each lane's 16 bytes go straight to the lane's slot of a 1 KB
+// stretch of the tile, and rows outside [0, n) read as zero through the buffer's range
+// check.  Four tile planes rotate in LDS: plane z+2 is loaded while plane z is computed
+// from planes z-1, z and z+1, so the z neighbours need no registers either.
+template <typename T, int TC, int K>
+struct GridDma {
+  using S = SpmmShape<T, TC>;
+  static constexpr int RX = S::RPB;
+  static constexpr int TX = RX + 2, TY = K + 2;
+  static constexpr int CPR = S::LPR;
+  static constexpr int CH = TY * TX * CPR;              // 16-byte chunks of a tile plane
+  static constexpr int NJ = (CH + 63) / 64;             // wave loads per plane
+  static constexpr int CE = 16 / (int)sizeof(T);
+  static constexpr int CCH = 7 * K * RX / CE;           // coefficient chunks per plane
+  static constexpr int NCJ = (CCH + 63) / 64;
+  static constexpr int R = 4;                           // planes in the ring
+  static constexpr size_t kPlane = (size_t)NJ * 1024;
+  static constexpr size_t kCoef = (size_t)NCJ * 1024;
+  static constexpr size_t kLds = R * (kPlane + kCoef);
+};
+
+// s_waitcnt vmcnt(0) with the other counters left alone (gfx9 encoding)
+__device__ __forceinline__ void wait_vm0() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+template <typename T, int TC, int K>
+__global__ void __launch_bounds__(kBlock)
+k_spmm_grid_dma(int n, int gnx, int gny, int gnz, int zseg, int nxb, int nyb, int nwork,
+                const T* __restrict__ dv, const T* __restrict__ X, T* __restrict__ Y) {
+  using G = GridDma<T, TC, K>;
+  using S = typename G::S;
+  typedef T Vec __attribute__((ext_vector_type(S::VL)));
+  extern __shared__ __align__(1024) unsigned char lds_raw[];
+  const int w = xcd_block();
+  if (w >= nwork) return;  // the whole workgroup leaves together
+  const int bx = w % nxb, by = (w / nxb) % nyb, bz = w / (nxb * nyb);
+  const int tid = (int)threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int li = tid % G::CPR, xl = tid / G::CPR;
+  const int b = gnx, c = gnx * gny;
+  const int x0 = bx * G::RX, y0 = by * K;
+  const int z0 = bz * zseg, z1 = min(gnz, z0 + zseg);
+  const int x = x0 + xl;
+  const __amdgpu_buffer_rsrc_t xr =
+      __builtin_amdgcn_make_buffer_rsrc((void*)X, 0, (int)((size_t)n * TC * sizeof(T)), 0x00020000);
+  const __amdgpu_buffer_rsrc_t cr =
+      __builtin_amdgcn_make_buffer_rsrc((void*)dv, 0, (int)((size_t)7 * n * sizeof(T)), 0x00020000);
+  constexpr unsigned kOut = 0xFFFFFFF0u;  // past the end of either buffer: reads as zero
+  auto plane_at = [&](int zz) -> unsigned char* {
+    return lds_raw + (size_t)((zz - z0 + 1) & (G::R - 1)) * (G::kPlane + G::kCoef);
+  };
+  // enqueue plane zz (tile with halo, then the coefficients of the tile's own rows)
+  auto load_plane = [&](int zz) {
+    unsigned char* base = plane_at(zz);
+    for (int j = wave; j < G::NJ; j += 4) {
+      const int f = j * 64 + lane;
+      unsigned off = kOut;
+      if (f < G::CH) {
+        const int pos = f / G::CPR, ch = f % G::CPR;
+        const int yi = pos / G::TX, xi = pos % G::TX;
+        const long long r = (long long)zz * c + (long long)(y0 + yi - 1) * b + (x0 + xi - 1);
+        if (r >= 0 && r < n) off = (unsigned)((r * TC + ch * S::VL) * (long long)sizeof(T));
+      }
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(xr, (__attribute__((address_space(3))) void*)(base + (size_t)j * 1024),
+                                               16, off, 0, 0, 0);
+    }
+    for (int j = wave; j < G::NCJ; j += 4) {
+      const int q = j * 64 + lane;
+      unsigned off = kOut;
+      if (q < G::CCH) {
+        constexpr int per = G::RX / G::CE;
+        const int xc = (q % per) * G::CE, dk = q / per, d = dk / K, k = dk % K;
+        if (zz < gnz && y0 + k < gny && x0 + xc < gnx) {
+          const long long r = (long long)zz * c + (long long)(y0 + k) * b + x0 + xc;
+          off = (unsigned)(((long long)d * n + r) * (long long)sizeof(T));
+        }
+      }
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          cr, (__attribute__((address_space(3))) void*)(base + G::kPlane + (size_t)j * 1024), 16, off, 0, 0, 0);
+    }
+  };
+  auto row_at = [&](int zz, int yi, int xi) -> Vec {
+    const Vec* p = reinterpret_cast<const Vec*>(plane_at(zz));
+    return p[(yi * G::TX + xi) * G::CPR + li];
+  };
+  load_plane(z0 - 1);
+  load_plane(z0);
+  load_plane(z0 + 1);
+  for (int z = z0; z < z1; ++z) {
+    wait_vm0();  // this wave's loads of plane z + 1 (and of the planes before) have landed
+    __syncthreads();  // ... and every wave's; the slot of plane z + 2 is no longer read
+    if (z + 2 <= z1) load_plane(z + 2);
+    if (x < gnx) {
+      const T* cf = reinterpret_cast<const T*>(plane_at(z) + G::kPlane);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (y0 + k >= gny) break;  // the same for the whole workgroup
+        const long long r = (long long)z * c + (long long)(y0 + k) * b + x;
+        auto coef = [&](int d) { return cf[(d * K + k) * G::RX + xl]; };
+        auto term = [&](int d, long long j, const Vec& xv, Vec& acc) {
+          fma_row<T, Vec, S::VL>(acc, (j >= 0 && j < n) ? coef(d) : T(0), xv);
+        };
+        Vec acc = Vec(0);
+        term(0, r - c, row_at(z - 1, k + 1, xl + 1), acc);
+        term(1, r - b, row_at(z, k, xl + 1), acc);
+        term(2, r - 1, row_at(z, k + 1, xl), acc);
+        term(3, r, row_at(z, k + 1, xl + 1), acc);
+        term(4, r + 1, row_at(z, k + 1, xl + 2), acc);
+        term(5, r + b, row_at(z, k + 2, xl + 1), acc);
+        term(6, r + c, row_at(z + 1, k + 1, xl + 1), acc);
+        __builtin_nontemporal_store(acc, reinterpret_cast<Vec*>(Y + (size_t)r * TC + li * S::VL));
+      }
     }
   }
 }
@@ -984,6 +1292,63 @@ struct SmallTile {
   static constexpr int ROWS = 4 * 16 * RT;  // rows per workgroup
 };
 
+// Store a 16 x 16 matrix-core result tile (rows row0.., columns col0.. of a row-major
+// array with leading dimension ld) with 16-byte lane stores instead of one value per lane:
+// lanes of a quad exchange values by DPP so that each holds consecutive columns of one row.
+// FP64 (lane (g, c) holds rows g + 4v of column c): lanes c and c^1 swap two values, and
+// each stores columns (c & ~1, +1) of two rows.  FP32 (rows 4g + v of column c): a 4 x 4
+// transpose in two exchange stages (lanes j^1, then j^2, j = c & 3), after which lane j
+// stores columns (c & ~3 .. +3) of row 4g + j.  Every lane of the wavefront takes part
+// (the exchanges need them all); only the stores test the row bound.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+constexpr int kDppXor1 = 0xB1;  // quad_perm [1, 0, 3, 2]
+constexpr int kDppXor2 = 0x4E;  // quad_perm [2, 3, 0, 1]
+
+__device__ __forceinline__ void store_tile16(double* out, int n, int ld, int row0, int col0, int g, int c,
+                                             const mf_d4& a) {
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  const bool odd = c & 1;
+  const double q0 = dpp_d<kDppXor1>(odd ? a[0] : a[1]);
+  const double q1 = dpp_d<kDppXor1>(odd ? a[2] : a[3]);
+  const int ra = row0 + g + (odd ? 4 : 0), rb = row0 + g + (odd ? 12 : 8);
+  const d2 va = odd ? d2{q0, a[1]} : d2{a[0], q0};
+  const d2 vb = odd ? d2{q1, a[3]} : d2{a[2], q1};
+  const int col = col0 + (c & ~1);
+  if (ra < n) *reinterpret_cast<d2*>(out + (size_t)ra * ld + col) = va;
+  if (rb < n) *reinterpret_cast<d2*>(out + (size_t)rb * ld + col) = vb;
+}
+
+__device__ __forceinline__ void store_tile16(float* out, int n, int ld, int row0, int col0, int g, int c,
+                                             const mf_f4& a) {
+  const int j = c & 3;
+  const bool j0 = j & 1, j1 = j & 2;
+  // stage 1: send the values whose index differs from j in bit 0, take the partner's
+  const float p0 = dpp_f<kDppXor1>(j0 ? a[0] : a[1]);
+  const float p1 = dpp_f<kDppXor1>(j0 ? a[2] : a[3]);
+  const float b0 = j0 ? p0 : a[0], b1 = j0 ? a[1] : p0;
+  const float b2 = j0 ? p1 : a[2], b3 = j0 ? a[3] : p1;
+  // stage 2: the same in bit 1
+  const float s0 = dpp_f<kDppXor2>(j1 ? b0 : b2);
+  const float s1 = dpp_f<kDppXor2>(j1 ? b1 : b3);
+  mf_f4 v;
+  v[0] = j1 ? s0 : b0;
+  v[1] = j1 ? s1 : b1;
+  v[2] = j1 ? b2 : s0;
+  v[3] = j1 ? b3 : s1;
+  const int row = row0 + 4 * g + j;
+  if (row < n) *reinterpret_cast<mf_f4*>(out + (size_t)row * ld + col0 + (c & ~3)) = v;
+}
+
 template <typename T, typename TX, int TC, bool FINAL>
 __global__ void __launch_bounds__(kBlock)
 k_small_mfma(int n, int nwg, int ntiles, const T* __restrict__ H, const T* __restrict__ Yin, const double* __restrict__ M,
@@ -1045,26 +1410,25 @@ k_small_mfma(int n, int nwg, int ntiles, const T* __restrict__ H, const T* __res
       }
     }
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
+    for (int rt = 0; rt < RT; ++rt) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = rowbase + rt * 16 + Mfma<T>::row(g, v);
-        if (row < n) {
+      for (int tb = 0; tb < TB; ++tb) {
+        store_tile16(Wout, n, TC, rowbase + rt * 16, tb * 16, g, c, aw[rt][tb]);
+        if constexpr (FINAL) store_tile16(Zout, n, TC, rowbase + rt * 16, tb * 16, g, c, az[rt][tb]);
+      }
+      if constexpr (FINAL) {
 #pragma unroll
-          for (int tb = 0; tb < TB; ++tb) {
-            Wout[(size_t)row * TC + tb * 16 + c] = aw[rt][tb][v];
-            if constexpr (FINAL) Zout[(size_t)row * TC + tb * 16 + c] = az[rt][tb][v];
-          }
-          if constexpr (FINAL) {
-            if (c == 0) {  // column 0 of the beta tile: (H beta)_row and (Y beta)_row
-              x[row] += (TX)aw[rt][TB][v];
-              const T rn = r[row] - az[rt][TB][v];
-              r[row] = rn;
-              rr += (double)rn * (double)rn;
-            }
+        for (int v = 0; v < 4; ++v) {
+          const int row = rowbase + rt * 16 + Mfma<T>::row(g, v);
+          if (row < n && c == 0) {  // column 0 of the beta tile: (H beta)_row and (Y beta)_row
+            x[row] += (TX)aw[rt][TB][v];
+            const T rn = r[row] - az[rt][TB][v];
+            r[row] = rn;
+            rr += (double)rn * (double)rn;
           }
         }
       }
+    }
   }
   if constexpr (FINAL) {
     const double tot = block_sum(rr, red);
@@ -1247,8 +1611,8 @@ void launch_zero(void* p, size_t bytes, hipStream_t s) {
 void launch_cast_d2f(int n, const double* in, float* out, hipStream_t s) {
   hipLaunchKernelGGL(k_cast_d2f, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, s, n, in, out);
 }
-void launch_axpy_f2d(int n, const float* d, double* x, hipStream_t s) {
-  hipLaunchKernelGGL(k_axpy_f2d, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, s, n, d, x);
+void launch_axpy_f2d(int n, const float* d, double* x, hipStream_t s, double alpha) {
+  hipLaunchKernelGGL(k_axpy_f2d, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, s, n, alpha, d, x);
 }
 void launch_axpy_d(int n, const double* d, double* x, hipStream_t s) {
   hipLaunchKernelGGL(k_axpy_d, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, s, n, d, x);
@@ -1277,12 +1641,36 @@ const float* dia_vals_of<float>(const DevCsr& A) { return A.dvalf; }
 
 constexpr int kGridK = 2;     // rows (y) per lane of the 3-D grid-stencil product
 constexpr int kGridZseg = 16;  // planes per workgroup of the grid-stencil product
+constexpr int kGridLdsK = 4;   // y rows per tile of the LDS-staged grid-stencil product
+constexpr int kGridDmaK = 2;   // y rows per tile of the product fed by direct loads to LDS
 
 // The automatic choice.  The grid kernel pays off on 3-D stencils once a row spans at least
 // 4 lanes (so that its coefficients take one load per lane); on 2-D operators of the sizes
 // here the diagonal kernel is as fast or faster (the 2-D grid walk has too few workgroups).
-inline int spmm_choice(const DevCsr& A, int lpr) {
-  if (A.gnx > 0 && A.ndiag == 7 && lpr >= 4) return kSpmmGrid;
+
+// The LDS-staged grid kernel needs a 3-D 7-point grid stencil with unit x stride, at least 4
+// lanes per block row and rows of whole 16-byte coefficient chunks.
+bool spmm_grid_lds_ok(const DevCsr& A, int tc, int elt) {
+  const int vl = std::min(16 / elt, tc);
+  return A.gnx > 0 && A.ndiag == 7 && A.ga == 1 && tc / vl >= 4 && A.gnx % (16 / elt) == 0;
+}
+
+// The direct-load variant also reads X and the coefficients through 32-bit buffer offsets.
+bool spmm_grid_dma_ok(const DevCsr& A, int tc, int elt) {
+  return spmm_grid_lds_ok(A, tc, elt) && (double)A.n * tc * elt <= 4294967040.0 &&
+         (double)A.n * 7 * elt <= 4294967040.0;
+}
+
+// The automatic choice: the most specific form the matrix has; among the 3-D grid-stencil
+// kernels the one measured fastest at this width and precision on the 128^3 and 160^3
+// operators (register planes, LDS-staged, or LDS fed by direct loads).
+inline int spmm_choice(const DevCsr& A, int tc, int elt) {
+  const int lpr = tc / std::min(16 / elt, tc);
+  if (A.gnx > 0 && A.ndiag == 7 && lpr >= 4) {
+    if (elt == 8 && (tc == 16 || tc == 32) && spmm_grid_lds_ok(A, tc, elt)) return kSpmmGridLds;
+    if (elt == 4 && (tc == 32 || tc == 64) && spmm_grid_dma_ok(A, tc, elt)) return kSpmmGridDma;
+    return kSpmmGrid;
+  }
   return A.ndiag > 0 ? kSpmmDia : kSpmmCsr;
 }
 
@@ -1293,9 +1681,29 @@ void launch_spmm(const DevCsr& A, int tc, const T* X, T* Y, hipStream_t s, int k
   case TC: {                                                                                     \
     using Sh = SpmmShape<T, TC>;                                                                 \
     const int nwg = cdiv(A.n, Sh::RPB);                                                          \
-    if (kernel == kSpmmAuto) kernel = spmm_choice(A, Sh::LPR);                                   \
+    if (kernel == kSpmmAuto) kernel = spmm_choice(A, TC, (int)sizeof(T));                        \
     stat_begin(s);                                                                               \
-    if (kernel == kSpmmGrid) {                                                                   \
+    if (kernel == kSpmmGridLds) {                                                                \
+      if constexpr (Sh::LPR >= 4) {                                                              \
+        using GL = GridLds<T, TC, kGridLdsK>;                                                    \
+        const int nxb = cdiv(A.gnx, GL::RX), nyb = cdiv(A.gny, kGridLdsK);                       \
+        const int nwork = nxb * nyb * cdiv(A.gnz, kGridZseg);                                    \
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_spmm_grid_lds<T, TC, kGridLdsK>), \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)GL::kLds);    \
+        hipLaunchKernelGGL((k_spmm_grid_lds<T, TC, kGridLdsK>), dim3(pad8(nwork)), dim3(kBlock), GL::kLds, s, \
+                           A.n, A.gnx, A.gny, A.gnz, kGridZseg, nxb, nyb, nwork, dia_vals_of<T>(A), X, Y); \
+      }                                                                                          \
+    } else if (kernel == kSpmmGridDma) {                                                         \
+      if constexpr (Sh::LPR >= 4) {                                                              \
+        using GD = GridDma<T, TC, kGridDmaK>;                                                    \
+        const int nxb = cdiv(A.gnx, GD::RX), nyb = cdiv(A.gny, kGridDmaK);                       \
+        const int nwork = nxb * nyb * cdiv(A.gnz, kGridZseg);                                    \
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_spmm_grid_dma<T, TC, kGridDmaK>), \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)GD::kLds);    \
+        hipLaunchKernelGGL((k_spmm_grid_dma<T, TC, kGridDmaK>), dim3(pad8(nwork)), dim3(kBlock), GD::kLds, s, \
+                           A.n, A.gnx, A.gny, A.gnz, kGridZseg, nxb, nyb, nwork, dia_vals_of<T>(A), X, Y); \
+      }                                                                                          \
+    } else if (kernel == kSpmmGrid) {                                                            \
       const int K = A.ndiag == 7 ? kGridK : 1;                                                   \
       const int nxb = cdiv(A.gnx, Sh::RPB), nyb = cdiv(A.gny, K), nzb = cdiv(A.gnz, kGridZseg);  \
       const int nwork = nxb * nyb * nzb;                                                         \

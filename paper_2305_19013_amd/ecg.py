@@ -67,6 +67,7 @@ class Options(C.Structure):
         ("restart_tol", C.c_double),
         ("max_restarts", C.c_int32),
         ("restart_at_switch", C.c_int32),
+        ("refine_keep_q", C.c_int32),
     ]
 
 
@@ -372,7 +373,7 @@ def debug_spmm(op: Operator, t: int, X, Y):
     check(lib().ecg_debug_spmm(op.handle, t, _ptr(X), _ptr(Y), _stream()))
 
 
-SPMM_AUTO, SPMM_CSR, SPMM_DIA, SPMM_GRID = -1, 0, 1, 2
+SPMM_AUTO, SPMM_CSR, SPMM_DIA, SPMM_GRID, SPMM_GRID_LDS, SPMM_GRID_DMA = -1, 0, 1, 2, 3, 4
 
 
 def debug_spmm_kernel(op: Operator, kernel: int, t: int, X, Y):

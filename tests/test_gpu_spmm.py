@@ -1,8 +1,9 @@
-"""GPU checks of the three sparse-times-block product kernels (CSR, diagonal form, grid
-stencil) on the products the solver takes (Alg. 1 and 3: Z = A P on an n x t block).
+"""GPU checks of the sparse-times-block product kernels (CSR, diagonal form, grid stencil
+with registers, grid stencil staged in LDS) on the products the solver takes (Alg. 1 and 3:
+Z = A P on an n x t block).
 
-The diagonal-form and grid-stencil kernels sum the same terms in the same ascending column
-order as the CSR kernel, so for finite inputs the three must agree bitwise, in FP64 and in
+The diagonal-form and both grid-stencil kernels sum the same terms in the same ascending
+column order as the CSR kernel, so for finite inputs they must agree bitwise, in FP64 and in
 FP32.  The FP64 product is also held to the forward error bound of a dot product of at
 most 7 terms against SciPy: |Y - A X| <= 16 u |A| |X|.
 """
@@ -15,8 +16,12 @@ import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-CSR_K, DIA_K, GRID_K = 0, 1, 2
+CSR_K, DIA_K, GRID_K, LDS_K, DMA_K = 0, 1, 2, 3, 4
 TS = [1, 2, 4, 8, 16, 32, 64]
+# cases where the LDS-staged grid kernel applies (3-D 7-point, unit x stride, nx a multiple
+# of the 16-byte coefficient chunk); it needs at least 4 lanes per block row: t >= 8 in
+# FP64, t >= 16 in FP32
+LDS_CASES = {"box_20x12x7", "box_24x13x40", "box_64x6x33"}
 
 
 @pytest.fixture(scope="module")
@@ -66,6 +71,10 @@ CASES = {
     "box_17x13x40": lambda: _grid3d(40, 13, 17, 2),
     # one x line per plane row pair, many planes
     "box_3x2x50": lambda: _grid3d(50, 2, 3, 3),
+    # ny not a multiple of the LDS tile's 4 y rows, nz = 40: ragged y tiles and z segments
+    "box_24x13x40": lambda: _grid3d(40, 13, 24, 4),
+    # several x tiles per line, ny = 6 (one full and one ragged y tile), nz = 33
+    "box_64x6x33": lambda: _grid3d(33, 6, 64, 5),
     # the 2-D jumping-coefficient operator (5 diagonals: the 2-D form of the kernel)
     "jump2d_64": lambda: W.config("jump2d512", scale=8).A.to_scipy(),
     # 2-D, lines of 33, 17 lines
@@ -82,8 +91,12 @@ CASES = {
 def test_grid_stencil_product_fp64(torch_dev, case, t):
     torch, dev = torch_dev
     A = CASES[case]()
-    X, Y = _products(torch, dev, _csr(A), t, np.float64, (GRID_K, DIA_K, CSR_K), seed=t)
+    lds = case in LDS_CASES and t >= 8
+    X, Y = _products(torch, dev, _csr(A), t, np.float64, (GRID_K, DIA_K, CSR_K) + ((LDS_K, DMA_K) if lds else ()),
+                     seed=t)
     assert np.array_equal(Y[GRID_K], Y[DIA_K]) and np.array_equal(Y[DIA_K], Y[CSR_K])
+    if lds:
+        assert np.array_equal(Y[LDS_K], Y[DIA_K]) and np.array_equal(Y[DMA_K], Y[DIA_K])
     bound = 16 * 2.0 ** -53 * (abs(A) @ np.abs(X))
     assert np.all(np.abs(Y[GRID_K] - A @ X) <= bound + 1e-300)
 
@@ -93,8 +106,12 @@ def test_grid_stencil_product_fp64(torch_dev, case, t):
 def test_grid_stencil_product_fp32(torch_dev, case, t):
     torch, dev = torch_dev
     A = CASES[case]()
-    X, Y = _products(torch, dev, _csr(A), t, np.float32, (GRID_K, DIA_K, CSR_K), seed=100 + t)
+    lds = case in LDS_CASES and t >= 16
+    X, Y = _products(torch, dev, _csr(A), t, np.float32, (GRID_K, DIA_K, CSR_K) + ((LDS_K, DMA_K) if lds else ()),
+                     seed=100 + t)
     assert np.array_equal(Y[GRID_K], Y[DIA_K]) and np.array_equal(Y[DIA_K], Y[CSR_K])
+    if lds:
+        assert np.array_equal(Y[LDS_K], Y[DIA_K]) and np.array_equal(Y[DMA_K], Y[DIA_K])
     A32 = A.astype(np.float32).astype(np.float64)  # the FP32 copy of the values
     bound = 16 * 2.0 ** -24 * (abs(A32) @ np.abs(X.astype(np.float64)))
     assert np.all(np.abs(Y[GRID_K] - A32 @ X.astype(np.float64)) <= bound)
@@ -131,13 +148,20 @@ def test_kernel_availability(torch_dev):
     with pytest.raises(ecg.EcgError, match="diagonal"):
         _products(torch, dev, S, 4, np.float64, (DIA_K,), seed=1)
     with pytest.raises(ecg.EcgError):
-        _products(torch, dev, _csr(_grid3d(4, 4, 4, 0)), 4, np.float64, (3,), seed=1)
+        _products(torch, dev, _csr(_grid3d(4, 4, 4, 0)), 4, np.float64, (5,), seed=1)
+    # the LDS-staged grid kernel: not for 2 lanes per row (FP64 t = 4), an odd nx, a non-unit
+    # x stride or a 2-D operator
+    for A, t in ((_grid3d(4, 4, 8, 0), 4), (_grid3d(4, 4, 17, 0), 32), (CASES["offsets_2_6_60"](), 32),
+                 (CASES["jump2d_64"](), 32)):
+        for kern in (LDS_K, DMA_K):
+            with pytest.raises(ecg.EcgError, match="LDS"):
+                _products(torch, dev, _csr(A), t, np.float64, (kern,), seed=1)
 
 
-@pytest.mark.parametrize("t", [16, 32])
+@pytest.mark.parametrize("t", [16, 32, 64])
 def test_grid_stencil_full_size_equals_diagonal_form(torch_dev, t):
-    """The 128^3 anisotropic operator of the benchmark: grid and diagonal kernels bitwise
-    equal on the whole block, FP64 and FP32."""
+    """The 128^3 anisotropic operator of the benchmark: both grid kernels and the diagonal
+    kernel bitwise equal on the whole block, FP64 and FP32."""
     torch, dev = torch_dev
     from paper_2305_19013_amd import ecg
 
@@ -146,11 +170,14 @@ def test_grid_stencil_full_size_equals_diagonal_form(torch_dev, t):
     for dt in (torch.float64, torch.float32):
         g = torch.Generator(device=dev).manual_seed(t)
         Xt = torch.randn((p.n, t), dtype=dt, device=dev, generator=g)
-        Yg, Yd = torch.empty_like(Xt), torch.empty_like(Xt)
+        Yg, Yd, Yl, Ym = (torch.empty_like(Xt) for _ in range(4))
         ecg.debug_spmm_kernel(op, GRID_K, t, Xt, Yg)
         ecg.debug_spmm_kernel(op, DIA_K, t, Xt, Yd)
+        ecg.debug_spmm_kernel(op, LDS_K, t, Xt, Yl)
+        ecg.debug_spmm_kernel(op, DMA_K, t, Xt, Ym)
         torch.cuda.synchronize()
-        assert bool(torch.equal(Yg, Yd))
+        assert bool(torch.equal(Yg, Yd)) and bool(torch.equal(Yl, Yd)) and bool(torch.equal(Ym, Yd))
+        del Xt, Yg, Yd, Yl, Ym
 
 
 @pytest.mark.parametrize("variant", [0, 1])
