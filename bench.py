@@ -35,6 +35,8 @@ Sections, in order (a section that no longer fits the budget is recorded as skip
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--budget-s S] [--workload NAME]
                        [--t T] [--precond none|bj_ic0|chol64] [--forms fp64,fp32] [--no-cpu]
                        [--no-side] [--kmax N] [--copy-calibration] [--oracle-full]
+       python bench.py --explore --workload NAME [--t T] [--precond ...] [--forms ...] [--kmax N]
+                       (one solve per form, no timed series: the long configurations)
 """
 
 from __future__ import annotations
@@ -342,8 +344,9 @@ def poisson_section(args, torch, ecg, dev):
 
 def learned_section(args, torch, dev):
     """learn2d256 (256x256, log10 k ~ U(-3,3) on 16x16-cell blocks, t = 16): ECG with the
-    trained G G^T against its untrained Jacobi start, block-Jacobi IC(0) and no
-    preconditioner, on held-out operator seeds 2000.. (FP64, tol 1e-8).  The parameters were
+    trained G G^T against its untrained Jacobi start, the classical factor on the same
+    pattern (FSAI), block-Jacobi IC(0) and no preconditioner, on held-out operator seeds
+    2000.. (FP64, tol 1e-8).  The parameters were
     trained on the GPU by `python -m paper_2305_19013_amd.learned` and are read from
     paper_2305_19013_amd/trained/learn2d256.json."""
     import workloads as W
@@ -357,7 +360,7 @@ def learned_section(args, torch, dev):
     nx, ny = p0.grid
     model = LN.LearnedFactor(nx, ny, np.asarray(meta["params"]), dev)
     seeds = list(range(2000, 2000 + args.learned_ops))
-    kinds = ("learned", "jacobi", "bj_ic0")
+    kinds = ("learned", "jacobi", "fsai", "bj_ic0")
     LN.evaluate(model, seeds[:1], dev, 1, kinds, params_jacobi=W.init_params(meta["init_seed"]))  # priming
     res = LN.evaluate(model, seeds, dev, 1, kinds, params_jacobi=W.init_params(meta["init_seed"]))
     res.update(LN.evaluate(model, seeds[:1], dev, 1, ("plain",), kmax=6000))
@@ -453,6 +456,56 @@ def oracle_full_section(args, torch, ecg, dev):
     return out
 
 
+def explore(args):
+    """One solve per requested form of one workload (no timed series): iterations, switch
+    iterations, stored vectors, dropped blocks, true relative residual and seconds, with
+    progress lines every --progress iterations.  For configurations too long for the timed
+    series (jump3d160, aniso3d128 at t = 16 / 64)."""
+    import torch
+
+    import workloads as W
+    from paper_2305_19013_amd import ecg
+
+    ecg.lib()
+    dev = torch.device("cuda:0")
+    prob = W.config(args.workload, t=args.t) if args.workload == "aniso3d128" else W.config(args.workload)
+    op = ecg.Operator.from_csr(prob.A)
+    P = ecg.Partition(prob.part, prob.t)
+    b = torch.from_numpy(prob.b).to(dev)
+    M = None
+    if args.precond == "bj_ic0":
+        M = ecg.Precond.bj_ic0(op, P)
+    elif args.precond == "chol64":
+        M = ecg.Precond.bj(op, W.box_partition(prob.grid, (8, 8)), ecg.BJ_CHOL)
+    out = {"mode": "explore", "workload": args.workload, "n": prob.n, "t": prob.t, "precond": args.precond,
+           "kmax": args.kmax}
+    for form in [f for f in args.forms.split(",") if f]:
+        kw, w = form_options(args, ecg, prob, form, M)
+        free, _ = torch.cuda.mem_get_info()
+        col = prob.n * w
+        qbytes = max(prob.t * col, int(free * 0.93) - 4 * prob.t * col - (3 << 30))
+        opts = ecg.options(q_budget_bytes=qbytes, **kw)
+        ws = torch.empty(ecg.workspace_size(op, P, opts), dtype=torch.uint8, device=dev)
+        x = torch.zeros_like(b)
+        ecg.progress(args.progress)
+        log(f"[explore {args.workload} {form}] q budget {qbytes / 1e9:.1f} GB = {qbytes // col} columns")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep = solve_once(ecg, op, P, b, x, opts, ws)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ecg.progress(0)
+        out[form] = {"seconds": round(dt, 3), "iters": rep["iters"], "switch_iters": rep["switch_iters"],
+                     "t_final": rep["t_final"], "outer_iters": rep["outer_iters"],
+                     "vectors_stored": rep["vectors_stored"], "blocks_dropped": rep["blocks_dropped"],
+                     "q_cols": qbytes // col, "relres_recursive": rep["relres_recursive"],
+                     "relres_true": rep["relres_true"], "status": rep["status"]}
+        log(f"[explore {args.workload} {form}] {out[form]}")
+        del ws
+        torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -476,6 +529,8 @@ def main():
     ap.add_argument("--precond", default="none", choices=("none", "bj_ic0", "chol64"),
                     help="preconditioner of the main solve (block-Jacobi IC(0) on the subdomains, or "
                          "exact Cholesky of 64 blocks of a 2D grid)")
+    ap.add_argument("--explore", action="store_true",
+                    help="one solve per form of --workload (no timed series; see explore())")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="copy 1 GiB device-to-device before the solves (HBM counter calibration)")
     args = ap.parse_args()
@@ -484,6 +539,9 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.explore:
+        explore(args)
+        return
     budget = Budget(args.budget_s)
     forms = [f for f in args.forms.split(",") if f]
     main_form = "fp64" if "fp64" in forms else forms[0]
@@ -532,8 +590,9 @@ def main():
         def fit_main(est):
             return int((budget.left() - later - 10.0) // est)
 
+        # --warmup 0 (profiler runs): the priming solve and the timed steps only, no roofline
         R = run_form(args, torch, ecg, prob, op, P, b, main_form, M=M, steps=args.steps,
-                     warmup=max(1, args.warmup), tag="", instrument=True, fit=fit_main)
+                     warmup=args.warmup, tag="", instrument=args.warmup > 0, fit=fit_main)
         rep = R["report"]
         out.update({"value": round(R["seconds"], 4), "steps": R["steps"], "warmup": R["warmup"],
                     "ms_per_step": round(R["seconds"] * 1e3, 2)})

@@ -59,6 +59,14 @@ ecg_status ecg_nn_backward(int32_t nx, int32_t ny, int32_t nb, const double* a5,
 ecg_status ecg_nn_adam(int32_t nparam, float* params, const double* grad, double* m, double* v, int32_t step,
                        double lr, double beta1, double beta2, double eps, void* hip_stream);
 
+/* The classical factor on the same pattern, as the baseline of the network (factorised sparse
+ * approximate inverse, Kolotilina and Yeremin): g3 = the G that minimises the Kaporin condition
+ * number of G^T A G among lower-triangular G on the pattern, in closed form for a 5-point
+ * operator (column j of G is A_C^{-1} e_1 scaled to unit A-norm, C = {j, j+1, j+nx}).  a5, g3
+ * as above; every Schur complement a_jj - a_jE^2/a_EE - a_jN^2/a_NN must be positive (true for
+ * SPD A; not checked). */
+ecg_status ecg_nn_fsai(int32_t nx, int32_t ny, int32_t nb, const double* a5, double* g3, void* hip_stream);
+
 /* CSR of G for one operator (g3 holds [3][n]): rowptr int64[n+1], colind int32[nnz],
  * vals double[nnz] with nnz = 3n - ny - nx, each row sorted with the diagonal last (the
  * layout ecg_precond_create_factor expects).  All device pointers. */

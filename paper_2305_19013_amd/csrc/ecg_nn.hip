@@ -347,6 +347,34 @@ k_factor_csr(int nx, int n, const double* __restrict__ g3, long long* __restrict
   val[k] = g3[i];
 }
 
+// Factorised sparse approximate inverse on the same pattern (Kolotilina and Yeremin): column
+// j of G, with rows {j, j+1 (east), j+nx (north)}, is A_C^{-1} e_1 scaled to unit A-norm, C
+// those rows.  For a 5-point operator the east and north neighbours do not couple, so
+// A_C^{-1} e_1 = (1, -a_jE / a_EE, -a_jN / a_NN) / s_j with the Schur complement
+// s_j = a_jj - a_jE^2 / a_EE - a_jN^2 / a_NN, and the column is that vector times sqrt(s_j).
+// Row i of G then holds 1/sqrt(s_i) (diagonal), -a_{i-1,i} / (a_ii sqrt(s_{i-1})) (west) and
+// -a_{i-nx,i} / (a_ii sqrt(s_{i-nx})) (south), with a_{i-1,i} = a_iW and a_{i-nx,i} = a_iS by
+// symmetry.  The minimiser of the Kaporin condition number of G^T A G over the pattern.
+__device__ __forceinline__ double fsai_schur(const double* __restrict__ a5, int n, int nx, int j) {
+  double s = a5[j];
+  if (j % nx < nx - 1) s -= a5[2 * n + j] * a5[2 * n + j] / a5[j + 1];
+  if (j + nx < n) s -= a5[4 * n + j] * a5[4 * n + j] / a5[j + nx];
+  return s;
+}
+
+__global__ void __launch_bounds__(kB)
+k_fsai(int nx, int n, int nb, const double* __restrict__ a5, double* __restrict__ g3) {
+  const long long e = (long long)blockIdx.x * kB + threadIdx.x;
+  if (e >= (long long)nb * n) return;
+  const int op = (int)(e / n), i = (int)(e % n);
+  const double* A = a5 + (size_t)op * 5 * n;
+  double* G = g3 + (size_t)op * 3 * n;
+  const double aii = A[i];
+  G[i] = 1.0 / sqrt(fsai_schur(A, n, nx, i));
+  G[n + i] = (i % nx > 0) ? -A[n + i] / (aii * sqrt(fsai_schur(A, n, nx, i - 1))) : 0.0;
+  G[2 * n + i] = (i >= nx) ? -A[3 * n + i] / (aii * sqrt(fsai_schur(A, n, nx, i - nx))) : 0.0;
+}
+
 // workspace layout of loss_grad/backward: u, e, Ae, w, Ax (5 nb n doubles), dot partials,
 // loss factors, backward partials
 struct NnPlan {
@@ -473,6 +501,18 @@ ecg_status ecg_nn_adam(int32_t nparam, float* params, const double* grad, double
   const double c1 = 1.0 - std::pow(beta1, step), c2 = 1.0 - std::pow(beta2, step);
   hipLaunchKernelGGL(k_adam, dim3(cdiv(nparam, kB)), dim3(kB), 0, s, nparam, params, grad, m, v, lr, beta1, beta2,
                      eps, c1, c2);
+  NNCHK(hipGetLastError());
+  NNCHK(hipStreamSynchronize(s));
+  return ECG_OK;
+}
+
+ecg_status ecg_nn_fsai(int32_t nx, int32_t ny, int32_t nb, const double* a5, double* g3, void* hip_stream) {
+  if (!a5 || !g3) return nn_fail(ECG_EINVAL, "NULL argument");
+  ecg_status st = check_dims(nx, ny, nb);
+  if (st != ECG_OK) return st;
+  hipStream_t s = (hipStream_t)hip_stream;
+  const int n = nx * ny;
+  hipLaunchKernelGGL(k_fsai, dim3(cdiv((long long)nb * n, kB)), dim3(kB), 0, s, nx, n, nb, a5, g3);
   NNCHK(hipGetLastError());
   NNCHK(hipStreamSynchronize(s));
   return ECG_OK;

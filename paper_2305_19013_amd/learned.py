@@ -38,6 +38,7 @@ def _lib():
             "ecg_nn_backward": [i32, i32, i32, vp, vp, vp, C.c_double, vp, vp, C.c_size_t, vp],
             "ecg_nn_adam": [i32, vp, vp, vp, vp, i32, C.c_double, C.c_double, C.c_double, C.c_double, vp],
             "ecg_nn_factor_csr": [i32, i32, vp, vp, vp, vp, vp],
+            "ecg_nn_fsai": [i32, i32, i32, vp, vp, vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -111,14 +112,30 @@ class LearnedFactor:
 
     def preconditioner(self, a5_one):
         """E.Precond for one operator (a5_one: [1, 5, n]) built from the network's G."""
-        torch = self.torch
-        g3 = self.forward(a5_one)
-        nnz = 3 * self.n - self.nx - self.ny
-        rowptr = torch.empty(self.n + 1, dtype=torch.int64, device=self.device)
-        col = torch.empty(nnz, dtype=torch.int32, device=self.device)
-        val = torch.empty(nnz, dtype=torch.float64, device=self.device)
-        E.check(_lib().ecg_nn_factor_csr(self.nx, self.ny, _p(g3), _p(rowptr), _p(col), _p(val), E._stream()))
-        return E.Precond.factor_device(self.n, nnz, rowptr, col, val)
+        return factor_precond(self.nx, self.ny, self.forward(a5_one), self.device)
+
+
+def fsai_g3(nx: int, ny: int, a5):
+    """G of the classical factorised sparse approximate inverse on the same pattern
+    (ecg_nn_fsai), for a5 [nb, 5, n] on the device; returns g3 [nb, 3, n]."""
+    import torch
+
+    g3 = torch.empty((a5.shape[0], 3, nx * ny), dtype=torch.float64, device=a5.device)
+    E.check(_lib().ecg_nn_fsai(nx, ny, a5.shape[0], _p(a5), _p(g3), E._stream()))
+    return g3
+
+
+def factor_precond(nx: int, ny: int, g3, device):
+    """E.Precond with M^{-1} = G G^T from g3 [1, 3, n] (CSR built on the device)."""
+    import torch
+
+    n = nx * ny
+    nnz = 3 * n - nx - ny
+    rowptr = torch.empty(n + 1, dtype=torch.int64, device=device)
+    col = torch.empty(nnz, dtype=torch.int32, device=device)
+    val = torch.empty(nnz, dtype=torch.float64, device=device)
+    E.check(_lib().ecg_nn_factor_csr(nx, ny, _p(g3), _p(rowptr), _p(col), _p(val), E._stream()))
+    return E.Precond.factor_device(n, nnz, rowptr, col, val)
 
 
 # ----------------------------------------------------------------------------- data
@@ -200,7 +217,10 @@ def _val_iters(model, seeds, device, scale):
 
 def evaluate(model: LearnedFactor, seeds, device, scale=1, kinds=("learned", "jacobi", "bj_ic0", "plain"),
              kmax=4000, params_jacobi=None, log=None):
-    """Iterations and seconds of ECG (t = 16, FP64, tol 1e-8) per preconditioner kind."""
+    """Iterations and seconds of ECG (t = 16, FP64, tol 1e-8) per preconditioner kind: learned
+    (the network's G G^T), jacobi (the network at params_jacobi, its untrained start), fsai (the
+    classical factor on the same pattern), bj_ic0 (block-Jacobi IC(0) on the subdomains) or
+    plain (none)."""
     import torch
 
     out = {k: [] for k in kinds}
@@ -222,6 +242,8 @@ def evaluate(model: LearnedFactor, seeds, device, scale=1, kinds=("learned", "ja
                 M = jac.preconditioner(a5t)
             elif k == "bj_ic0":
                 M = E.Precond.bj_ic0(op, P)
+            elif k == "fsai":
+                M = factor_precond(model.nx, model.ny, fsai_g3(model.nx, model.ny, a5t), device)
             else:
                 M = None
             torch.cuda.synchronize()

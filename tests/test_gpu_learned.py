@@ -130,6 +130,30 @@ def test_three_adam_steps_match_oracle(env):
         assert np.abs(m.params.cpu().numpy() - th).max() <= 2e-7 * np.abs(th).max(), step
 
 
+def test_fsai_baseline_satisfies_its_defining_conditions(env):
+    """The classical factor on the learned factor's pattern (Kolotilina-Yeremin FSAI): each
+    column g_j of G, supported on {j, east, north}, makes A g_j vanish on the column's other
+    rows and has unit A-norm, so G^T A G has a unit diagonal.  Checked with dense products
+    on two 32 x 32 operators of the family."""
+    torch, dev, learned = env
+    ps, a5, b, x = _batch([14, 15])
+    nx, ny = ps[0].grid
+    g3 = learned.fsai_g3(nx, ny, torch.from_numpy(a5).to(dev)).cpu().numpy()
+    n = nx * ny
+    for s in range(2):
+        A = ps[s].A.to_scipy().toarray()
+        G = Lr.g_matrix(*g3[s], nx).toarray()
+        assert np.allclose(np.triu(G, 1), 0) and np.all(np.diag(G) > 0)
+        AG = A @ G
+        assert np.allclose(np.diag(G.T @ AG), 1.0, rtol=1e-13, atol=0)
+        j = np.arange(n)
+        e = j[j % nx < nx - 1]
+        nn = j[j + nx < n]
+        scale = np.abs(A).max() * np.abs(G).max()
+        assert np.abs(AG[e + 1, e]).max() <= 1e-14 * scale
+        assert np.abs(AG[nn + nx, nn]).max() <= 1e-14 * scale
+
+
 def test_factor_csr_is_exact(env):
     torch, dev, learned = env
     ps, a5, b, x = _batch([10])
