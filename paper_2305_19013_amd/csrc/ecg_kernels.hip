@@ -367,11 +367,14 @@ struct GridLds {
   static constexpr size_t kLds = 2 * (kRowBytes + kCoefBytes);
 };
 
-template <typename T, int TC, int K>
+// CW: columns of the block one workgroup takes (CW < TC splits wide blocks into column
+// groups, so that a tile of 512-byte FP64 rows keeps the x extent of a 256-byte one).
+template <typename T, int TC, int CW, int K>
 __global__ void __launch_bounds__(kBlock)
 k_spmm_grid_lds(int n, int gnx, int gny, int gnz, int zseg, int nxb, int nyb, int nwork,
                 const T* __restrict__ dv, const T* __restrict__ X, T* __restrict__ Y) {
-  using G = GridLds<T, TC, K>;
+  static_assert(TC % CW == 0, "column groups");
+  using G = GridLds<T, CW, K>;
   using S = typename G::S;
   typedef T Vec __attribute__((ext_vector_type(S::VL)));
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -379,19 +382,23 @@ k_spmm_grid_lds(int n, int gnx, int gny, int gnz, int zseg, int nxb, int nyb, in
   T* coef_lds = reinterpret_cast<T*>(lds_raw + 2 * G::kRowBytes);         // [2][K][RX][8]
   const int w = xcd_block();
   if (w >= nwork) return;  // the whole workgroup leaves together
-  const int bx = w % nxb, by = (w / nxb) % nyb, bz = w / (nxb * nyb);
+  const int tiles = nwork / (TC / CW);
+  const int cg = w / tiles, wt = w % tiles;  // column group slowest: neighbouring tiles adjacent
+  const int bx = wt % nxb, by = (wt / nxb) % nyb, bz = wt / (nxb * nyb);
   const int tid = (int)threadIdx.x;
   const int li = tid % G::CPR, xl = tid / G::CPR;
   const int b = gnx, c = gnx * gny;
   const int x0 = bx * G::RX, y0 = by * K;
   const int z0 = bz * zseg, z1 = min(gnz, z0 + zseg);
   const int x = x0 + xl;
+  const T* __restrict__ Xg = X + cg * CW;
+  T* __restrict__ Yg = Y + cg * CW;
   // linear index of tile position (yi, xi) of plane zz (halo included)
   auto lin = [&](int zz, int yi, int xi) -> long long {
     return (long long)zz * c + (long long)(y0 + yi - 1) * b + (x0 + xi - 1);
   };
   auto ldx = [&](long long r, int chunk) -> Vec {
-    return (r >= 0 && r < n) ? *reinterpret_cast<const Vec*>(X + (size_t)r * TC + chunk * S::VL) : Vec(0);
+    return (r >= 0 && r < n) ? *reinterpret_cast<const Vec*>(Xg + (size_t)r * TC + chunk * S::VL) : Vec(0);
   };
   auto halo_pos = [&](int h, int& yi, int& xi) {
     if (h < G::TX) {
@@ -504,7 +511,7 @@ k_spmm_grid_lds(int n, int gnx, int gny, int gnz, int zseg, int nxb, int nyb, in
         term(4, r + 1, slot(buf, k + 1, xl + 2, li), acc);
         term(5, r + b, slot(buf, k + 2, xl + 1, li), acc);
         term(6, r + c, nxt[k], acc);
-        __builtin_nontemporal_store(acc, reinterpret_cast<Vec*>(Y + (size_t)r * TC + li * S::VL));
+        __builtin_nontemporal_store(acc, reinterpret_cast<Vec*>(Yg + (size_t)r * TC + li * S::VL));
       }
     }
     if (more) {
@@ -798,8 +805,10 @@ struct GramTile {
 // K of the 16x16x4 product runs over rows (4 rows per instruction, lane group g = l/16
 // takes row r+g).  M and N are interleaved so that each lane reads TA (TB) consecutive
 // values of a row with one vector load: tile ta pairs M-index i with Q column TA*i+ta,
-// tile tb pairs N-index j with Y column TB*j+tb.  Sixteen rows are loaded before the
-// products of the first four start, to keep enough loads in flight.
+// tile tb pairs N-index j with Y column TB*j+tb.  A candidate narrower than 16 columns
+// (TC = 8 after halvings) fills the N lanes past TC with zeros and writes only its own
+// columns.  Sixteen rows are loaded before the products of the first four start, to keep
+// enough loads in flight.
 template <typename T, int WQ, int TC>
 __global__ void __launch_bounds__(64)
 k_gram_mfma(int n, Span<T> sp, int rows_per_chunk, int units, int nwork, const T* __restrict__ Y,
@@ -807,7 +816,8 @@ k_gram_mfma(int n, Span<T> sp, int rows_per_chunk, int units, int nwork, const T
   using V = typename Mfma<T>::V;
   using GT = GramTile<T, WQ, TC>;
   constexpr int JB = GT::JB, BPG = GT::BPG;
-  constexpr int TA = GT::TA, TB = TC / 16;
+  constexpr bool NARROW = TC < 16;
+  constexpr int TA = GT::TA, TB = NARROW ? 1 : TC / 16;
   typedef T TAv __attribute__((ext_vector_type(TA)));
   typedef T TBv __attribute__((ext_vector_type(TB)));
   constexpr int RQ = 4;  // row quads loaded ahead
@@ -836,7 +846,8 @@ k_gram_mfma(int n, Span<T> sp, int rows_per_chunk, int units, int nwork, const T
     jv[jb] = blk < sp.nblk;
     Qb[jb] = sp.base + (size_t)(jv[jb] ? blk : j0) * sp.stride + (TA * c) % WQ;
   }
-  const T* __restrict__ Yc = Y + TB * c;
+  const T* __restrict__ Yc = Y + (NARROW ? (c < TC ? c : 0) : TB * c);
+  const bool cy = !NARROW || c < TC;  // this lane's N column is one of Y's
   // operands of 4*RQ rows, double-buffered: the next batch is requested before the
   // products of the current one are issued
   TAv qa0[RQ][JB], qa1[RQ][JB];
@@ -846,7 +857,7 @@ k_gram_mfma(int n, Span<T> sp, int rows_per_chunk, int units, int nwork, const T
     for (int q = 0; q < RQ; ++q) {
       const int rr = row + 4 * q + g;
       const bool ok = rr < r1;
-      yb[q] = ok ? *reinterpret_cast<const TBv*>(Yc + (size_t)rr * TC) : TBv(0);
+      yb[q] = (ok && cy) ? *reinterpret_cast<const TBv*>(Yc + (size_t)rr * TC) : TBv(0);
 #pragma unroll
       for (int jb = 0; jb < JB; ++jb)  // Q is streamed once: keep it out of the caches
         qa[q][jb] = (ok && jv[jb]) ? __builtin_nontemporal_load(reinterpret_cast<const TAv*>(Qb[jb] + (size_t)rr * WQ))
@@ -883,8 +894,9 @@ k_gram_mfma(int n, Span<T> sp, int rows_per_chunk, int units, int nwork, const T
         const int vc = TA * Mfma<T>::row(g, v) + ta;  // column of the virtual block
         if (j0 + jb * BPG + vc / WQ >= sp.nblk) continue;
         const size_t a = rowbase + vc;
+        if (!cy) continue;
 #pragma unroll
-        for (int tb = 0; tb < TB; ++tb) part[a * TC + TB * c + tb] = acc[jb][ta][tb][v];
+        for (int tb = 0; tb < TB; ++tb) part[a * TC + (NARROW ? c : TB * c + tb)] = acc[jb][ta][tb][v];
       }
   }
 }
@@ -894,7 +906,10 @@ k_gram_mfma(int n, Span<T> sp, int rows_per_chunk, int units, int nwork, const T
 // row of Q (a 16/32-byte vector load), so instruction s of a 16-column chunk pairs lane
 // group g with column 4g+s; the matching rows of G come from LDS.  G is staged KS
 // columns at a time in two LDS buffers: the next stage is fetched into registers while
-// the current one is multiplied, so each stage costs one barrier.
+// the current one is multiplied, so each stage costs one barrier.  Narrow shapes after
+// halvings: stored blocks of 8 columns are taken in pairs as one 16-column pass (lane group
+// g reads its 4 columns from block 4g / WQ of the pair), and a candidate of 8 columns fills
+// the N lanes past TC with zero rows of G and writes only its own columns.
 template <typename T, int WQ, int TC>
 struct UpdateTile {
   static constexpr int KS = (WQ > 64 ? WQ : 64);        // stored columns per stage
@@ -909,7 +924,11 @@ k_update_mfma(int n, int nwg, Span<T> sp, const T* __restrict__ G, T* __restrict
   using V = typename Mfma<T>::V;
   typedef T T4 __attribute__((ext_vector_type(4)));
   using U = UpdateTile<T, WQ, TC>;
-  constexpr int TB = TC / 16, RT = 4;
+  constexpr bool NARROW = TC < 16;
+  constexpr int TB = NARROW ? 1 : TC / 16, RT = 4;
+  constexpr int VQ = WQ >= 16 ? WQ : 16;  // stored columns of one pass
+  constexpr int PB = VQ / WQ;              // stored blocks of one pass
+  static_assert(U::JS % PB == 0, "passes do not straddle stages");
   __shared__ T Gs[2][U::NE];
   const int blk = xcd_block();
   if (blk >= nwg) return;  // the whole workgroup leaves together
@@ -947,22 +966,26 @@ k_update_mfma(int n, int nwg, Span<T> sp, const T* __restrict__ G, T* __restrict
     const int cur = st & 1;
     if (st + 1 < nst) fetch(st + 1);
     const int jn = min(U::JS, sp.nblk - st * U::JS);
-    for (int jb = 0; jb < jn; ++jb) {
-      const T* __restrict__ Qj = sp.base + (size_t)(st * U::JS + jb) * sp.stride;
+    for (int jb = 0; jb < jn; jb += PB) {
 #pragma unroll
-      for (int kc = 0; kc < WQ / 16; ++kc) {
+      for (int kc = 0; kc < VQ / 16; ++kc) {
+        const int col = kc * 16 + 4 * g;  // column of this pass
+        const int bj = jb + col / WQ;     // stored block of the stage
+        const bool bok = bj < jn;
+        const T* __restrict__ Qj = sp.base + (size_t)(st * U::JS + (bok ? bj : jb)) * sp.stride + col % WQ;
         T4 q[RT];
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
           const int row = rowbase + rt * 16 + c;
-          q[rt] = row < n ? *reinterpret_cast<const T4*>(Qj + (size_t)row * WQ + kc * 16 + 4 * g) : T4{0, 0, 0, 0};
+          q[rt] = (row < n && bok) ? *reinterpret_cast<const T4*>(Qj + (size_t)row * WQ) : T4{0, 0, 0, 0};
         }
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-          const int kk = jb * WQ + kc * 16 + 4 * g + s;
+          const int kk = jb * WQ + col + s;
           T gv[TB];
 #pragma unroll
-          for (int tb = 0; tb < TB; ++tb) gv[tb] = Gs[cur][kk * TC + tb * 16 + c];
+          for (int tb = 0; tb < TB; ++tb)
+            gv[tb] = (NARROW && c >= TC) ? T(0) : Gs[cur][kk * TC + (NARROW ? c : tb * 16 + c)];
 #pragma unroll
           for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -979,8 +1002,9 @@ k_update_mfma(int n, int nwg, Span<T> sp, const T* __restrict__ G, T* __restrict
     for (int v = 0; v < 4; ++v) {
       const int row = rowbase + rt * 16 + Mfma<T>::row(g, v);
       if (row < n) {
+        if (NARROW && c >= TC) continue;
 #pragma unroll
-        for (int tb = 0; tb < TB; ++tb) W[(size_t)row * TC + tb * 16 + c] -= acc[rt][tb][v];
+        for (int tb = 0; tb < TB; ++tb) W[(size_t)row * TC + (NARROW ? c : tb * 16 + c)] -= acc[rt][tb][v];
       }
     }
 }
@@ -1292,63 +1316,6 @@ struct SmallTile {
   static constexpr int ROWS = 4 * 16 * RT;  // rows per workgroup
 };
 
-// Store a 16 x 16 matrix-core result tile (rows row0.., columns col0.. of a row-major
-// array with leading dimension ld) with 16-byte lane stores instead of one value per lane:
-// lanes of a quad exchange values by DPP so that each holds consecutive columns of one row.
-// FP64 (lane (g, c) holds rows g + 4v of column c): lanes c and c^1 swap two values, and
-// each stores columns (c & ~1, +1) of two rows.  FP32 (rows 4g + v of column c): a 4 x 4
-// transpose in two exchange stages (lanes j^1, then j^2, j = c & 3), after which lane j
-// stores columns (c & ~3 .. +3) of row 4g + j.  Every lane of the wavefront takes part
-// (the exchanges need them all); only the stores test the row bound.
-template <int CTRL>
-__device__ __forceinline__ float dpp_f(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-template <int CTRL>
-__device__ __forceinline__ double dpp_d(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
-  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-}
-constexpr int kDppXor1 = 0xB1;  // quad_perm [1, 0, 3, 2]
-constexpr int kDppXor2 = 0x4E;  // quad_perm [2, 3, 0, 1]
-
-__device__ __forceinline__ void store_tile16(double* out, int n, int ld, int row0, int col0, int g, int c,
-                                             const mf_d4& a) {
-  typedef double d2 __attribute__((ext_vector_type(2)));
-  const bool odd = c & 1;
-  const double q0 = dpp_d<kDppXor1>(odd ? a[0] : a[1]);
-  const double q1 = dpp_d<kDppXor1>(odd ? a[2] : a[3]);
-  const int ra = row0 + g + (odd ? 4 : 0), rb = row0 + g + (odd ? 12 : 8);
-  const d2 va = odd ? d2{q0, a[1]} : d2{a[0], q0};
-  const d2 vb = odd ? d2{q1, a[3]} : d2{a[2], q1};
-  const int col = col0 + (c & ~1);
-  if (ra < n) *reinterpret_cast<d2*>(out + (size_t)ra * ld + col) = va;
-  if (rb < n) *reinterpret_cast<d2*>(out + (size_t)rb * ld + col) = vb;
-}
-
-__device__ __forceinline__ void store_tile16(float* out, int n, int ld, int row0, int col0, int g, int c,
-                                             const mf_f4& a) {
-  const int j = c & 3;
-  const bool j0 = j & 1, j1 = j & 2;
-  // stage 1: send the values whose index differs from j in bit 0, take the partner's
-  const float p0 = dpp_f<kDppXor1>(j0 ? a[0] : a[1]);
-  const float p1 = dpp_f<kDppXor1>(j0 ? a[2] : a[3]);
-  const float b0 = j0 ? p0 : a[0], b1 = j0 ? a[1] : p0;
-  const float b2 = j0 ? p1 : a[2], b3 = j0 ? a[3] : p1;
-  // stage 2: the same in bit 1
-  const float s0 = dpp_f<kDppXor2>(j1 ? b0 : b2);
-  const float s1 = dpp_f<kDppXor2>(j1 ? b1 : b3);
-  mf_f4 v;
-  v[0] = j1 ? s0 : b0;
-  v[1] = j1 ? s1 : b1;
-  v[2] = j1 ? b2 : s0;
-  v[3] = j1 ? b3 : s1;
-  const int row = row0 + 4 * g + j;
-  if (row < n) *reinterpret_cast<mf_f4*>(out + (size_t)row * ld + col0 + (c & ~3)) = v;
-}
-
 template <typename T, typename TX, int TC, bool FINAL>
 __global__ void __launch_bounds__(kBlock)
 k_small_mfma(int n, int nwg, int ntiles, const T* __restrict__ H, const T* __restrict__ Yin, const double* __restrict__ M,
@@ -1410,25 +1377,26 @@ k_small_mfma(int n, int nwg, int ntiles, const T* __restrict__ H, const T* __res
       }
     }
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt) {
+    for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-      for (int tb = 0; tb < TB; ++tb) {
-        store_tile16(Wout, n, TC, rowbase + rt * 16, tb * 16, g, c, aw[rt][tb]);
-        if constexpr (FINAL) store_tile16(Zout, n, TC, rowbase + rt * 16, tb * 16, g, c, az[rt][tb]);
-      }
-      if constexpr (FINAL) {
+      for (int v = 0; v < 4; ++v) {
+        const int row = rowbase + rt * 16 + Mfma<T>::row(g, v);
+        if (row < n) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = rowbase + rt * 16 + Mfma<T>::row(g, v);
-          if (row < n && c == 0) {  // column 0 of the beta tile: (H beta)_row and (Y beta)_row
-            x[row] += (TX)aw[rt][TB][v];
-            const T rn = r[row] - az[rt][TB][v];
-            r[row] = rn;
-            rr += (double)rn * (double)rn;
+          for (int tb = 0; tb < TB; ++tb) {
+            Wout[(size_t)row * TC + tb * 16 + c] = aw[rt][tb][v];
+            if constexpr (FINAL) Zout[(size_t)row * TC + tb * 16 + c] = az[rt][tb][v];
+          }
+          if constexpr (FINAL) {
+            if (c == 0) {  // column 0 of the beta tile: (H beta)_row and (Y beta)_row
+              x[row] += (TX)aw[rt][TB][v];
+              const T rn = r[row] - az[rt][TB][v];
+              r[row] = rn;
+              rr += (double)rn * (double)rn;
+            }
           }
         }
       }
-    }
   }
   if constexpr (FINAL) {
     const double tot = block_sum(rr, red);
@@ -1685,13 +1653,14 @@ void launch_spmm(const DevCsr& A, int tc, const T* X, T* Y, hipStream_t s, int k
     stat_begin(s);                                                                               \
     if (kernel == kSpmmGridLds) {                                                                \
       if constexpr (Sh::LPR >= 4) {                                                              \
-        using GL = GridLds<T, TC, kGridLdsK>;                                                    \
+        constexpr int CW = (sizeof(T) == 8 && TC > 32) ? 32 : TC;                                \
+        using GL = GridLds<T, CW, kGridLdsK>;                                                    \
         const int nxb = cdiv(A.gnx, GL::RX), nyb = cdiv(A.gny, kGridLdsK);                       \
-        const int nwork = nxb * nyb * cdiv(A.gnz, kGridZseg);                                    \
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_spmm_grid_lds<T, TC, kGridLdsK>), \
+        const int nwork = nxb * nyb * cdiv(A.gnz, kGridZseg) * (TC / CW);                        \
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_spmm_grid_lds<T, TC, CW, kGridLdsK>), \
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)GL::kLds);    \
-        hipLaunchKernelGGL((k_spmm_grid_lds<T, TC, kGridLdsK>), dim3(pad8(nwork)), dim3(kBlock), GL::kLds, s, \
-                           A.n, A.gnx, A.gny, A.gnz, kGridZseg, nxb, nyb, nwork, dia_vals_of<T>(A), X, Y); \
+        hipLaunchKernelGGL((k_spmm_grid_lds<T, TC, CW, kGridLdsK>), dim3(pad8(nwork)), dim3(kBlock), GL::kLds, \
+                           s, A.n, A.gnx, A.gny, A.gnz, kGridZseg, nxb, nyb, nwork, dia_vals_of<T>(A), X, Y); \
       }                                                                                          \
     } else if (kernel == kSpmmGridDma) {                                                         \
       if constexpr (Sh::LPR >= 4) {                                                              \
@@ -1772,7 +1741,7 @@ void launch_split_t(int n, const int* part, int level, int tc, const T* v, T* ou
 // Work units of one span: Gram wavefronts/workgroups along the block axis.
 template <typename T>
 static int gram_units(const Span<T>& sp, int tc) {
-  if (sp.width >= 16 && tc >= 16) {
+  if (sp.width >= 8 && tc >= 8) {
     const int jb = ((tc >= 64 || sizeof(T) == 8) ? 64 : 128) / sp.width;
     const int JB = jb < 1 ? 1 : jb;
     return (sp.nblk + JB - 1) / JB;
@@ -1798,7 +1767,7 @@ static int gram_chunks(int n, int units, size_t part_cap, int m, int tc, int elt
 template <typename T, int WQ, int TC>
 static void gram_span(int n, const Span<T>& sp, int rpc, int nch, const T* Y, T* part, int m, hipStream_t s) {
   stat_begin(s);
-  if constexpr (WQ >= 16 && TC >= 16) {
+  if constexpr (WQ >= 8 && TC >= 8) {
     constexpr int NB = GramTile<T, WQ, TC>::NB;
     const int units = (sp.nblk + NB - 1) / NB;
     const int nwork = units * nch;
@@ -1865,7 +1834,7 @@ static void update_span(int n, const Span<T>& sp, const T* G, T* W, hipStream_t 
 #define C(WQ)                                                                                          \
   case WQ: {                                                                                           \
     stat_begin(s);                                                                                     \
-    if constexpr (WQ >= 16 && TC >= 16) {                                                              \
+    if constexpr (WQ >= 8 && TC >= 8) {                                                                \
       const int nwg = cdiv(n, 256);                                                                    \
       hipLaunchKernelGGL((k_update_mfma<T, WQ, TC>), dim3(pad8(nwg)), dim3(kBlock), 0, s, n, nwg, sp, G, W); \
     } else {                                                                                           \

@@ -110,7 +110,10 @@ def test_split_is_exact(torch_dev, level):
 
 
 GRAM_CASES = [(4099, 3, 8, 8), (4099, 2, 32, 16), (70001, 5, 32, 32), (3000, 1, 64, 64), (1027, 4, 16, 64),
-              (5000, 3, 64, 8), (1027, 3, 16, 32), (4099, 5, 16, 16), (2053, 7, 32, 32), (777, 1, 16, 16)]
+              (5000, 3, 64, 8), (1027, 3, 16, 32), (4099, 5, 16, 16), (2053, 7, 32, 32), (777, 1, 16, 16),
+              # 8-wide candidates and stored blocks (after halvings): pairs of 8-column blocks,
+              # an odd count of them, a single one, and 8-wide candidates against wider blocks
+              (1027, 7, 8, 8), (777, 1, 8, 8), (70001, 9, 8, 8), (4099, 5, 16, 8), (2053, 2, 32, 8)]
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
