@@ -1635,7 +1635,7 @@ bool spmm_grid_dma_ok(const DevCsr& A, int tc, int elt) {
 inline int spmm_choice(const DevCsr& A, int tc, int elt) {
   const int lpr = tc / std::min(16 / elt, tc);
   if (A.gnx > 0 && A.ndiag == 7 && lpr >= 4) {
-    if (elt == 8 && (tc == 16 || tc == 32) && spmm_grid_lds_ok(A, tc, elt)) return kSpmmGridLds;
+    if (elt == 8 && tc >= 16 && spmm_grid_lds_ok(A, tc, elt)) return kSpmmGridLds;
     if (elt == 4 && (tc == 32 || tc == 64) && spmm_grid_dma_ok(A, tc, elt)) return kSpmmGridDma;
     return kSpmmGrid;
   }
