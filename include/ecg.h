@@ -169,7 +169,7 @@ typedef struct {
 } ecg_report;
 
 /* Fill *o with defaults: tol 1e-8, kmax 20000, no reduction, switch_tol 1e-5, t_min 1,
- * min_gap 1, FP64, inner_tol 1e-4, max_outer 20, replace_every 0, trunc 0,
+ * min_gap 1, FP64, inner_tol 1e-4, max_outer 20, replace_every 25, trunc 0,
  * q_budget_bytes 0, deflate_tol 1e-14, no preconditioner, SRE-CG2, no restarts
  * (restart_every 0, restart_tol 1e-5, max_restarts 0, restart_at_switch 0),
  * refine_keep_q 2. */
@@ -304,7 +304,9 @@ ecg_status ecg_debug_spmm(const ecg_operator* A, int32_t t, const double* X, dou
  * dividing n), 3 = 3-D grid stencil with its planes staged in LDS, 4 = the same with the
  * planes brought into LDS by direct buffer loads (3 and 4: seven diagonals, a = 1, at least
  * 4 lanes of 16 bytes per block row and nx a multiple of 16 / (bytes per value); 4 also
- * needs n t and 7 n values to fit 32-bit byte offsets), -1 = the one the solver uses.
+ * needs n t and 7 n values to fit 32-bit byte offsets), 5 = SELL-C-sigma (C = 64 rows per
+ * slice, rows sorted by length within windows of 1024; kept for matrices without a diagonal
+ * form), -1 = the one the solver uses.
  * precision 0: X and Y are double, 1: float.  Row-major n x t blocks, t a power of two in
  * 1..64.  Every kernel builds a row as a chain of fused multiply-adds in the stored (CSR)
  * or ascending-offset order, so for rows stored in ascending column order and finite X all

@@ -716,7 +716,64 @@ ecg_status upload_csr(int64_t n, const std::vector<int64_t>& rp, const std::vect
   return ECG_OK;
 }
 
+// SELL-C-sigma form (see DevCsr) built on the host from the CSR arrays.
+ecg_status upload_sell(int64_t n, const std::vector<int64_t>& rp, const std::vector<int32_t>& ci,
+                       const std::vector<double>& v, hipStream_t s, DevCsr* out) {
+  const int64_t npos = (n + kSellC - 1) / kSellC * kSellC;
+  std::vector<int> order(npos, -1);
+  for (int64_t w0 = 0; w0 < n; w0 += kSellSigma) {
+    const int64_t w1 = std::min<int64_t>(n, w0 + kSellSigma);
+    std::vector<int> win;
+    for (int64_t i = w0; i < w1; ++i) win.push_back((int)i);
+    std::stable_sort(win.begin(), win.end(),
+                     [&](int a, int b) { return rp[a + 1] - rp[a] > rp[b + 1] - rp[b]; });
+    std::copy(win.begin(), win.end(), order.begin() + w0);
+  }
+  const int nslice = (int)(npos / kSellC);
+  std::vector<int> sptr(nslice + 1, 0), slen(nslice, 0);
+  for (int sl = 0; sl < nslice; ++sl) {
+    int w = 0;
+    for (int i = 0; i < kSellC; ++i) {
+      const int r = order[(size_t)sl * kSellC + i];
+      if (r >= 0) w = std::max(w, (int)(rp[r + 1] - rp[r]));
+    }
+    slen[sl] = w;
+    if ((int64_t)sptr[sl] + (int64_t)w * kSellC > 0x7fffffff) return ECG_OK;  // too large: keep CSR only
+    sptr[sl + 1] = sptr[sl] + w * kSellC;
+  }
+  const size_t total = (size_t)sptr[nslice];
+  std::vector<int> scol(std::max<size_t>(total, 1));
+  std::vector<double> sval(std::max<size_t>(total, 1));
+  for (int sl = 0; sl < nslice; ++sl)
+    for (int i = 0; i < kSellC; ++i) {
+      const int r = order[(size_t)sl * kSellC + i];
+      for (int k = 0; k < slen[sl]; ++k) {
+        const size_t e = (size_t)sptr[sl] + (size_t)k * kSellC + i;
+        const bool real = r >= 0 && k < rp[r + 1] - rp[r];
+        scol[e] = real ? ci[rp[r] + k] : (r >= 0 ? r : 0);
+        sval[e] = real ? v[rp[r] + k] : 0.0;
+      }
+    }
+  ecg_status st;
+  if ((st = copy_in(&out->sell_ptr, sptr.data(), sptr.size(), 0, s)) != ECG_OK) return st;
+  if ((st = copy_in(&out->sell_len, slen.data(), slen.size(), 0, s)) != ECG_OK) return st;
+  if ((st = copy_in(&out->sell_row, order.data(), order.size(), 0, s)) != ECG_OK) return st;
+  if ((st = copy_in(&out->sell_col, scol.data(), scol.size(), 0, s)) != ECG_OK) return st;
+  if ((st = copy_in(&out->sell_val, sval.data(), sval.size(), 0, s)) != ECG_OK) return st;
+  HIPCHK(hipMalloc(&out->sell_valf, sval.size() * sizeof(float)));
+  launch_cast_val((int)sval.size(), out->sell_val, out->sell_valf, s);
+  HIPCHK(hipStreamSynchronize(s));
+  out->nslice = nslice;
+  return ECG_OK;
+}
+
 void free_csr(DevCsr& A) {
+  (void)hipFree(A.sell_ptr);
+  (void)hipFree(A.sell_len);
+  (void)hipFree(A.sell_row);
+  (void)hipFree(A.sell_col);
+  (void)hipFree(A.sell_val);
+  (void)hipFree(A.sell_valf);
   (void)hipFree(A.rowptr);
   (void)hipFree(A.col);
   (void)hipFree(A.val);
@@ -916,6 +973,7 @@ ecg_status ecg_options_default(ecg_options* o) {
   o->precision = ECG_FP64;
   o->inner_tol = 1e-4;
   o->max_outer = 20;
+  o->replace_every = 25;
   o->deflate_tol = 1e-14;
   o->precond = ECG_PRECOND_NONE;
   o->variant = ECG_SRE_CG2;
@@ -937,7 +995,8 @@ ecg_status ecg_operator_create_csr(int64_t n, int64_t nnz, const int64_t* rowptr
       (st = to_host(op->col, colind, (size_t)nnz, on_device, s)) != ECG_OK ||
       (st = to_host(op->val, vals, (size_t)nnz, on_device, s)) != ECG_OK ||
       (st = check_csr(n, nnz, op->rowptr, op->col)) != ECG_OK ||
-      (st = upload_csr(n, op->rowptr, op->col, op->val, s, &op->A, nullptr, true)) != ECG_OK) {
+      (st = upload_csr(n, op->rowptr, op->col, op->val, s, &op->A, nullptr, true)) != ECG_OK ||
+      (op->A.ndiag == 0 && (st = upload_sell(n, op->rowptr, op->col, op->val, s, &op->A)) != ECG_OK)) {
     free_csr(op->A);
     delete op;
     return st;
@@ -1424,7 +1483,9 @@ ecg_status ecg_debug_spmm_kernel(const ecg_operator* A, int32_t kernel, int32_t 
                                  void* Y, void* hip_stream) {
   if (!A || !X || !Y) return fail(ECG_EINVAL, "NULL argument");
   if (t < 1 || t > 64 || (t & (t - 1))) return fail(ECG_EINVAL, "t must be a power of two in [1, 64]");
-  if (kernel < kSpmmAuto || kernel > kSpmmGridDma) return fail(ECG_EINVAL, "unknown product kernel");
+  if (kernel < kSpmmAuto || kernel > kSpmmSell) return fail(ECG_EINVAL, "unknown product kernel");
+  if (kernel == kSpmmSell && A->A.nslice == 0)
+    return fail(ECG_EINVAL, "the operator has no SELL-C-sigma form (it is kept for matrices without a diagonal form)");
   if (precision != 0 && precision != 1) return fail(ECG_EINVAL, "precision must be 0 (FP64) or 1 (FP32)");
   if (kernel == kSpmmDia && A->A.ndiag == 0) return fail(ECG_EINVAL, "the operator has no diagonal form");
   if (kernel == kSpmmGrid && A->A.gnx == 0) return fail(ECG_EINVAL, "the operator is not a grid stencil");

@@ -36,11 +36,27 @@ struct DevCsr {
   // b = gnx, c = gnx * gny and n = gnz * c, so that row z*c + y*b + x has its +-b and +-c
   // neighbours at (x, y +- 1, z) and (x, y, z +- 1); a = ga is any remaining offset.
   int gnx = 0, gny = 0, gnz = 0, ga = 0;
+  // SELL-C-sigma form of a general matrix (kept when there is no diagonal form; nslice = 0
+  // otherwise): rows sorted by length, longest first, within windows of kSellSigma rows, cut
+  // into slices of kSellC consecutive sorted rows; slice s holds sell_len[s] entries per row
+  // (its longest row), stored entry-major from sell_ptr[s]: entry k of the slice's row i at
+  // sell_ptr[s] + k * kSellC + i.  Rows shorter than the slice are padded with weight 0 on
+  // their own column.  sell_row[p] is the original row at sorted position p (-1 past n).
+  int nslice = 0;
+  int* sell_ptr = nullptr;
+  int* sell_len = nullptr;
+  int* sell_row = nullptr;
+  int* sell_col = nullptr;
+  double* sell_val = nullptr;
+  float* sell_valf = nullptr;
 };
+constexpr int kSellC = 64;      // rows per SELL slice
+constexpr int kSellSigma = 1024;  // sorting window of the SELL form
 
 // Which product kernel launch_spmm uses (the automatic choice takes the most specific one
 // the matrix has).
-enum SpmmKernel { kSpmmAuto = -1, kSpmmCsr = 0, kSpmmDia = 1, kSpmmGrid = 2, kSpmmGridLds = 3, kSpmmGridDma = 4 };
+enum SpmmKernel { kSpmmAuto = -1, kSpmmCsr = 0, kSpmmDia = 1, kSpmmGrid = 2, kSpmmGridLds = 3, kSpmmGridDma = 4,
+                  kSpmmSell = 5 };
 // whether the LDS-staged grid kernels apply to A at block width tc, elt bytes per value
 bool spmm_grid_lds_ok(const DevCsr& A, int tc, int elt);
 bool spmm_grid_dma_ok(const DevCsr& A, int tc, int elt);

@@ -193,6 +193,48 @@ k_spmm(int n, int nwg, const int* __restrict__ rp, const int* __restrict__ ci, c
   __builtin_nontemporal_store(acc, reinterpret_cast<Vec*>(Y + (size_t)row * TC + c));
 }
 
+// The same product for a matrix in SELL-C-sigma form (DevCsr): positions in the sorted row
+// order; the LPR lanes of a position read its entries from the slice entry-major, so the
+// rows of a wavefront read consecutive words for each entry, and write the result to the
+// position's original row.  A row's entries come in the CSR order and the slice padding adds
+// weight-zero terms on the row's own block row, so the result equals the CSR kernel's.
+template <typename T, int TC>
+__global__ void __launch_bounds__(kBlock)
+k_spmm_sell(int npos, int nwg, const int* __restrict__ sptr, const int* __restrict__ slen,
+            const int* __restrict__ srow, const int* __restrict__ scol, const T* __restrict__ sval,
+            const T* __restrict__ X, T* __restrict__ Y) {
+  using S = SpmmShape<T, TC>;
+  typedef T Vec __attribute__((ext_vector_type(S::VL)));
+  constexpr int KB = 8;
+  const int blk = xcd_block();
+  if (blk >= nwg) return;
+  const int pos = blk * S::RPB + (int)threadIdx.x / S::LPR;
+  if (pos >= npos) return;
+  const int row = srow[pos];
+  if (row < 0) return;  // padding position of the last slice
+  const int c = ((int)threadIdx.x % S::LPR) * S::VL;
+  const int sl = pos / kSellC, i = pos % kSellC;
+  const int base = sptr[sl] + i, len = slen[sl];
+  const T* __restrict__ Xc = X + c;
+  Vec acc = Vec(0);
+  for (int kb = 0; kb < len; kb += KB) {
+    int col[KB];
+    T val[KB];
+#pragma unroll
+    for (int u = 0; u < KB; ++u) {
+      const bool ok = kb + u < len;
+      col[u] = ok ? scol[base + (kb + u) * kSellC] : row;
+      val[u] = ok ? sval[base + (kb + u) * kSellC] : T(0);
+    }
+    Vec xv[KB];
+#pragma unroll
+    for (int u = 0; u < KB; ++u) xv[u] = *reinterpret_cast<const Vec*>(Xc + (size_t)col[u] * TC);
+#pragma unroll
+    for (int u = 0; u < KB; ++u) fma_row<T, Vec, S::VL>(acc, val[u], xv[u]);
+  }
+  __builtin_nontemporal_store(acc, reinterpret_cast<Vec*>(Y + (size_t)row * TC + c));
+}
+
 // Coefficients of a row of the diagonal form with few instructions: of the LPR lanes that
 // share a row, lane li loads diagonals li, li + LPR, ... (coalesced along the rows) and
 // the others read them across lanes.  Each wavefront load instruction costs the memory
@@ -1606,6 +1648,12 @@ template <>
 const double* dia_vals_of<double>(const DevCsr& A) { return A.dval; }
 template <>
 const float* dia_vals_of<float>(const DevCsr& A) { return A.dvalf; }
+template <typename T>
+static const T* sell_vals_of(const DevCsr& A);
+template <>
+const double* sell_vals_of<double>(const DevCsr& A) { return A.sell_val; }
+template <>
+const float* sell_vals_of<float>(const DevCsr& A) { return A.sell_valf; }
 
 constexpr int kGridK = 2;     // rows (y) per lane of the 3-D grid-stencil product
 constexpr int kGridZseg = 16;  // planes per workgroup of the grid-stencil product
@@ -1639,7 +1687,8 @@ inline int spmm_choice(const DevCsr& A, int tc, int elt) {
     if (elt == 4 && (tc == 32 || tc == 64) && spmm_grid_dma_ok(A, tc, elt)) return kSpmmGridDma;
     return kSpmmGrid;
   }
-  return A.ndiag > 0 ? kSpmmDia : kSpmmCsr;
+  if (A.ndiag > 0) return kSpmmDia;
+  return A.nslice > 0 ? kSpmmSell : kSpmmCsr;
 }
 
 template <typename T>
@@ -1694,10 +1743,14 @@ void launch_spmm(const DevCsr& A, int tc, const T* X, T* Y, hipStream_t s, int k
     else if (kernel == kSpmmDia)                                                                 \
       hipLaunchKernelGGL((k_spmm_dia<T, TC, kMaxDiag>), dim3(pad8(nwg)), dim3(kBlock), 0, s, A.n, nwg, \
                          A.ndiag, A.dia, dia_vals_of<T>(A), X, Y);                               \
-    else                                                                                         \
+    else if (kernel == kSpmmSell) {                                                              \
+      const int npos = A.nslice * kSellC, nws = cdiv(npos, Sh::RPB);                             \
+      hipLaunchKernelGGL((k_spmm_sell<T, TC>), dim3(pad8(nws)), dim3(kBlock), 0, s, npos, nws, A.sell_ptr, \
+                         A.sell_len, A.sell_row, A.sell_col, sell_vals_of<T>(A), X, Y);          \
+    } else                                                                                       \
       hipLaunchKernelGGL((k_spmm<T, TC>), dim3(pad8(nwg)), dim3(kBlock), 0, s, A.n, nwg, A.rowptr, \
                          A.col, vals_of<T>(A), X, Y);                                            \
-    stat_end(kStatSpmm, (kernel != kSpmmCsr ? (double)A.ndiag * A.n * sizeof(T)                 \
+    stat_end(kStatSpmm, (kernel != kSpmmCsr && kernel != kSpmmSell ? (double)A.ndiag * A.n * sizeof(T) \
                                             : (double)A.nnz * (sizeof(T) + 4) + 4.0 * (A.n + 1)) + \
                             2.0 * sizeof(T) * A.n * TC,                                          \
              2.0 * A.nnz * TC, s);                                                               \

@@ -373,7 +373,7 @@ def debug_spmm(op: Operator, t: int, X, Y):
     check(lib().ecg_debug_spmm(op.handle, t, _ptr(X), _ptr(Y), _stream()))
 
 
-SPMM_AUTO, SPMM_CSR, SPMM_DIA, SPMM_GRID, SPMM_GRID_LDS, SPMM_GRID_DMA = -1, 0, 1, 2, 3, 4
+SPMM_AUTO, SPMM_CSR, SPMM_DIA, SPMM_GRID, SPMM_GRID_LDS, SPMM_GRID_DMA, SPMM_SELL = -1, 0, 1, 2, 3, 4, 5
 
 
 def debug_spmm_kernel(op: Operator, kernel: int, t: int, X, Y):

@@ -56,8 +56,12 @@ def _solve(torch, dev, csr, b, part, t, x0=None, **kw):
 
 # ---------------------------------------------------------------- building blocks
 @pytest.mark.parametrize("t", [1, 8, 32, 64])
-def test_spmm_general_csr_matches_scipy(torch_dev, t):
-    """A matrix with scattered columns (more than 16 distinct diagonals): the CSR kernel."""
+@pytest.mark.parametrize("kind", ["uniform", "ragged"])
+def test_spmm_general_csr_matches_scipy(torch_dev, t, kind):
+    """Matrices with scattered columns (more than 16 distinct diagonals): the SELL-C-sigma
+    kernel the solver picks and the CSR kernel agree bitwise, and both hold the dot-product
+    bound against SciPy.  "ragged": row lengths from 1 to ~300 (a few dense rows), n not a
+    multiple of the 64-row slice, so the sorted windows and the slice padding matter."""
     torch, dev = torch_dev
     import scipy.sparse as sp
 
@@ -66,15 +70,24 @@ def test_spmm_general_csr_matches_scipy(torch_dev, t):
     n = 5003
     rng = np.random.default_rng(40 + t)
     R = sp.random(n, n, density=6.0 / n, random_state=rng, format="csr")
+    if kind == "ragged":
+        dense = sp.csr_matrix((rng.standard_normal((7, n)) * (rng.random((7, n)) < 0.06)))
+        rows = sp.csr_matrix((np.ones(7), (rng.choice(n, 7, replace=False), np.arange(7))), shape=(n, 7))
+        R = R + rows @ dense
     A = sp.csr_matrix(R + R.T + sp.eye(n) * 10.0)
     A.sort_indices()
     csr = W.CSR(n, A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data.astype(np.float64))
     X = rng.standard_normal((n, t))
     Xt = _t(torch, dev, X)
-    Yt = torch.empty_like(Xt)
-    ecg.debug_spmm(ecg.Operator.from_csr(csr), t, Xt, Yt)
+    op = ecg.Operator.from_csr(csr)
+    Ys = {}
+    for k in (ecg.SPMM_AUTO, ecg.SPMM_SELL, ecg.SPMM_CSR):
+        Yt = torch.full_like(Xt, np.nan)
+        ecg.debug_spmm_kernel(op, k, t, Xt, Yt)
+        Ys[k] = Yt.cpu().numpy()
+    assert np.array_equal(Ys[ecg.SPMM_SELL], Ys[ecg.SPMM_CSR]) and np.array_equal(Ys[ecg.SPMM_AUTO], Ys[ecg.SPMM_SELL])
     scale = abs(A) @ np.abs(X)
-    assert np.all(np.abs(Yt.cpu().numpy() - A @ X) <= 2.0 ** -53 * 16 * scale + 1e-300)
+    assert np.all(np.abs(Ys[ecg.SPMM_SELL] - A @ X) <= 2.0 ** -53 * 16 * scale + 1e-300)
 
 
 @pytest.mark.parametrize("t", [1, 8, 32, 64])

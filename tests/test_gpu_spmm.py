@@ -148,6 +148,9 @@ def test_kernel_availability(torch_dev):
     with pytest.raises(ecg.EcgError, match="diagonal"):
         _products(torch, dev, S, 4, np.float64, (DIA_K,), seed=1)
     with pytest.raises(ecg.EcgError):
+        _products(torch, dev, _csr(_grid3d(4, 4, 4, 0)), 4, np.float64, (6,), seed=1)
+    # the SELL-C-sigma form is kept only for matrices without a diagonal form
+    with pytest.raises(ecg.EcgError, match="SELL"):
         _products(torch, dev, _csr(_grid3d(4, 4, 4, 0)), 4, np.float64, (5,), seed=1)
     # the LDS-staged grid kernel: not for 2 lanes per row (FP64 t = 4), an odd nx, a non-unit
     # x stride or a 2-D operator
