@@ -1346,10 +1346,11 @@ k_final_update(int n, int nwg, const T* __restrict__ H, const T* __restrict__ Y,
 // vector load and instruction s pairs lane group g with column 4g+s (the same
 // permutation of K is applied to the rows of M, staged in LDS).
 // FINAL: the fused update of the block iteration.  The same M (= C^{-1}) multiplies H
-// and Y (W = H C^{-1} into the stored-block slot, Z = Y C^{-1} the next candidate), and
-// one more 16-column tile of the B operand carries beta in its first column, so that the
-// products H beta and Y beta come out of the same instructions: x += H beta,
-// r -= Y beta, and the squared norm of the new r is reduced per workgroup.
+// and Y (W = H C^{-1} into the stored-block slot, Z = Y C^{-1} the next candidate) on
+// matrix cores, and the row products H beta and Y beta are formed from the same loaded
+// values with vector FMAs (each lane takes its four columns, then the four lane groups of
+// a row are summed by two cross-lane exchanges): x += H beta, r -= Y beta, and the squared
+// norm of the new r is reduced per workgroup.
 template <int TC, bool FINAL = false>
 struct SmallTile {
   // row tiles per wavefront; the fused update carries two products, so half as many
@@ -1366,15 +1367,15 @@ k_small_mfma(int n, int nwg, int ntiles, const T* __restrict__ H, const T* __res
   using V = typename Mfma<T>::V;
   typedef T T4 __attribute__((ext_vector_type(4)));
   constexpr int TB = TC / 16;
-  constexpr int NT = FINAL ? TB + 1 : TB;  // output column tiles (FINAL: + the beta tile)
+  constexpr int NT = TB;  // output column tiles
   constexpr int LD = NT * 16;
   constexpr int RT = SmallTile<TC, FINAL>::RT;
   __shared__ T Ms[TC * LD];
+  __shared__ __align__(32) T Bs[FINAL ? TC : 1];
   __shared__ double red[FINAL ? kBlock : 1];
-  for (int e = threadIdx.x; e < TC * LD; e += kBlock) {
-    const int kk = e / LD, j = e % LD;
-    Ms[e] = (T)(j < TC ? M[kk * TC + j] : ((FINAL && j == TC) ? beta[kk] : 0.0));
-  }
+  for (int e = threadIdx.x; e < TC * LD; e += kBlock) Ms[e] = (T)M[e];
+  if constexpr (FINAL)
+    for (int e = threadIdx.x; e < TC; e += kBlock) Bs[e] = (T)beta[e];
   __syncthreads();
   const int blk = xcd_block();
   if (blk >= nwg) return;  // uniform over the workgroup: no later barrier is split
@@ -1386,13 +1387,16 @@ k_small_mfma(int n, int nwg, int ntiles, const T* __restrict__ H, const T* __res
   for (int tile = blk; tile < ntiles; tile += nwg) {
     const int rowbase = tile * SmallTile<TC, FINAL>::ROWS + wave * 16 * RT;
     V aw[RT][NT], az[FINAL ? RT : 1][FINAL ? NT : 1];
+    T hb[RT], yb[RT];  // FINAL: this lane's part of (H beta)_row and (Y beta)_row
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
+    for (int rt = 0; rt < RT; ++rt) {
+      hb[rt] = T(0), yb[rt] = T(0);
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
         aw[rt][nt] = V{0, 0, 0, 0};
         if constexpr (FINAL) az[rt][nt] = V{0, 0, 0, 0};
       }
+    }
 #pragma unroll
     for (int kc = 0; kc < TC / 16; ++kc) {
       T4 qh[RT], qy[FINAL ? RT : 1];
@@ -1402,6 +1406,16 @@ k_small_mfma(int n, int nwg, int ntiles, const T* __restrict__ H, const T* __res
         const size_t off = (size_t)row * TC + kc * 16 + 4 * g;
         qh[rt] = row < n ? *reinterpret_cast<const T4*>(H + off) : T4{0, 0, 0, 0};
         if constexpr (FINAL) qy[rt] = row < n ? *reinterpret_cast<const T4*>(Yin + off) : T4{0, 0, 0, 0};
+      }
+      if constexpr (FINAL) {
+        const T4 bq = *reinterpret_cast<const T4*>(Bs + kc * 16 + 4 * g);
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4) {
+            hb[rt] = fmac(qh[rt][s4], bq[s4], hb[rt]);
+            yb[rt] = fmac(qy[rt][s4], bq[s4], yb[rt]);
+          }
       }
 #pragma unroll
       for (int s4 = 0; s4 < 4; ++s4) {
@@ -1429,16 +1443,25 @@ k_small_mfma(int n, int nwg, int ntiles, const T* __restrict__ H, const T* __res
             Wout[(size_t)row * TC + tb * 16 + c] = aw[rt][tb][v];
             if constexpr (FINAL) Zout[(size_t)row * TC + tb * 16 + c] = az[rt][tb][v];
           }
-          if constexpr (FINAL) {
-            if (c == 0) {  // column 0 of the beta tile: (H beta)_row and (Y beta)_row
-              x[row] += (TX)aw[rt][TB][v];
-              const T rn = r[row] - az[rt][TB][v];
-              r[row] = rn;
-              rr += (double)rn * (double)rn;
-            }
-          }
         }
       }
+    if constexpr (FINAL) {
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        // lanes c, c + 16, c + 32, c + 48 hold the four column groups of row c
+        T h = hb[rt] + __shfl_xor(hb[rt], 16, 64);
+        T y = yb[rt] + __shfl_xor(yb[rt], 16, 64);
+        h += __shfl_xor(h, 32, 64);
+        y += __shfl_xor(y, 32, 64);
+        const int row = rowbase + rt * 16 + c;
+        if (g == 0 && row < n) {
+          x[row] += (TX)h;
+          const T rn = r[row] - y;
+          r[row] = rn;
+          rr += (double)rn * (double)rn;
+        }
+      }
+    }
   }
   if constexpr (FINAL) {
     const double tot = block_sum(rr, red);
