@@ -944,98 +944,163 @@ k_gram_mfma(int n, Span<T> sp, int rows_per_chunk, int units, int nwork, const T
 }
 
 // CGS2 update W -= Q G on matrix cores.  A workgroup owns 256 rows (4 wavefronts x 4 row
-// tiles of 16); K runs over stored columns.  Each lane reads 4 consecutive columns of one
-// row of Q (a 16/32-byte vector load), so instruction s of a 16-column chunk pairs lane
-// group g with column 4g+s; the matching rows of G come from LDS.  G is staged KS
-// columns at a time in two LDS buffers: the next stage is fetched into registers while
-// the current one is multiplied, so each stage costs one barrier.  Narrow shapes after
-// halvings: stored blocks of 8 columns are taken in pairs as one 16-column pass (lane group
-// g reads its 4 columns from block 4g / WQ of the pair), and a candidate of 8 columns fills
-// the N lanes past TC with zero rows of G and writes only its own columns.
+// tiles of 16); K runs over the stored columns of the span in order.  Matrix-core operand
+// layout wants a lane to hold four consecutive columns of one row (instruction s of a
+// 16-column chunk pairs lane group g with column 4g+s; the matching rows of G come from
+// LDS), but read that way straight from memory every load instruction touches sixteen
+// 128-byte lines and uses half of each.  So Q goes through LDS: a wavefront reads its 64
+// rows x SC columns (SC x sizeof(T) = 128 bytes, one whole line per row) with 16-byte
+// non-temporal lane loads that use every byte of the lines they touch, writes them to its
+// own LDS tile, and reads them back in the operand layout.  Two such stages are in flight
+// in registers while the third is multiplied.  G is staged KS stored columns at a time in
+// two LDS buffers: the next stage is fetched into registers while the current one is
+// multiplied, so each G stage costs one barrier.  Narrow shapes after halvings: columns
+// of 8-column stored blocks follow each other in K like any others, and a candidate of 8
+// columns fills the N lanes past TC with zero rows of G and writes only its own columns.
 template <typename T, int WQ, int TC>
 struct UpdateTile {
-  static constexpr int KS = (WQ > 64 ? WQ : 64);        // stored columns per stage
-  static constexpr int JS = KS / WQ;                    // blocks per stage
-  static constexpr int NE = KS * TC;                    // G values per stage
-  static constexpr int PER = (NE + kBlock - 1) / kBlock;  // per thread
+  static constexpr int VQ = WQ >= 16 ? WQ : 16;
+  static constexpr int LINE = 128 / (int)sizeof(T);
+  static constexpr int SC = LINE < VQ ? LINE : VQ;  // stored columns of a Q stage
+  static constexpr int VL = 16 / (int)sizeof(T);    // values per 16-byte lane load
+  static constexpr int NL = SC / VL;                // lane loads per Q stage (64 rows)
+  static constexpr int LDQ = SC + VL;               // LDS row pitch of a Q tile (padded)
+  static constexpr int KS = TC >= 64 && SC <= 16 ? 32 : 64;  // stored columns per G stage
+  static constexpr int NE = KS * TC;                // G values per stage
+  static constexpr int PER = NE / kBlock;           // per thread
+  static constexpr int QPS = KS / SC;              // Q stages per G stage (even)
+  static_assert(KS % (2 * SC) == 0 && SC % 16 == 0 && NE % kBlock == 0, "stages");
 };
 
 template <typename T, int WQ, int TC>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(TC <= 32 ? 2 : 1)))
 k_update_mfma(int n, int nwg, Span<T> sp, const T* __restrict__ G, T* __restrict__ W) {
   using V = typename Mfma<T>::V;
-  typedef T T4 __attribute__((ext_vector_type(4)));
   using U = UpdateTile<T, WQ, TC>;
+  typedef T T4 __attribute__((ext_vector_type(4)));
+  typedef T L16 __attribute__((ext_vector_type(U::VL)));  // one 16-byte lane load
   constexpr bool NARROW = TC < 16;
   constexpr int TB = NARROW ? 1 : TC / 16, RT = 4;
-  constexpr int VQ = WQ >= 16 ? WQ : 16;  // stored columns of one pass
-  constexpr int PB = VQ / WQ;              // stored blocks of one pass
-  static_assert(U::JS % PB == 0, "passes do not straddle stages");
+  constexpr int SC = U::SC, NL = U::NL, LDQ = U::LDQ, KS = U::KS;
   __shared__ T Gs[2][U::NE];
+  __shared__ __align__(16) T Qs[4][64 * LDQ];
   const int blk = xcd_block();
-  if (blk >= nwg) return;  // the whole workgroup leaves together
+  if (blk >= nwg || sp.nblk <= 0) return;  // the whole workgroup leaves together
   const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
   const int g = lane >> 4, c = lane & 15;
   const int rowbase = blk * 256 + wave * 64;
-  const int nst = (sp.nblk + U::JS - 1) / U::JS;
+  const int ncol = sp.nblk * WQ;            // stored columns of the span
+  const int nq = (ncol + SC - 1) / SC;      // Q stages
+  const int nst = (ncol + KS - 1) / KS;     // G stages
   const T* __restrict__ Gspan = G + (size_t)sp.goff * TC;
-  const int total = sp.nblk * WQ * TC;  // G values of this span
+  const int total = ncol * TC;  // G values of this span
+  T* __restrict__ Qw = Qs[wave];
   V acc[RT][TB];
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
     for (int tb = 0; tb < TB; ++tb) acc[rt][tb] = V{0, 0, 0, 0};
+  // Loads are unconditional, so that nothing branches around them and the wait for a stage
+  // does not also wait for the loads issued after it.  G values past the span are loaded
+  // from its last one and replaced by zero when staged.  Q rows past n are loaded from row
+  // n - 1: a row of the product depends on its own row of Q only, and rows past n are not
+  // stored.  Columns past the last stored block (odd counts of 8-column blocks) are loaded
+  // from that block and meet zero rows of G.
   T pre[U::PER];
   auto fetch = [&](int st) {
 #pragma unroll
-    for (int i = 0; i < U::PER; ++i) {
-      const int e = (int)threadIdx.x + i * kBlock;
-      const int ge = st * U::NE + e;
-      pre[i] = (e < U::NE && ge < total) ? Gspan[ge] : T(0);
-    }
+    for (int i = 0; i < U::PER; ++i) pre[i] = Gspan[min(st * U::NE + (int)threadIdx.x + i * kBlock, total - 1)];
   };
-  auto stash = [&](int buf) {
+  auto stash = [&](int buf, int st) {
 #pragma unroll
     for (int i = 0; i < U::PER; ++i) {
       const int e = (int)threadIdx.x + i * kBlock;
-      if (e < U::NE) Gs[buf][e] = pre[i];
+      Gs[buf][e] = st * U::NE + e < total ? pre[i] : T(0);
     }
   };
+  // stage q: columns q*SC .. q*SC+SC-1 of the span for this wavefront's 64 rows; lane load
+  // i covers rows 64 / NL * i .. of the tile, SC / VL lanes per row
+  constexpr int LPR = SC / U::VL, RPL = 64 / LPR;  // lanes per tile row, tile rows per load
+  const int lr = lane / LPR, col = (lane % LPR) * U::VL;
+  auto loadq = [&](L16 (&v)[NL], int q) {
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+      const int rl = i * RPL + lr;
+      const int k = q * SC + col;
+      const int bj = min(k / WQ, sp.nblk - 1), row = min(rowbase + rl, n - 1);
+      v[i] = __builtin_nontemporal_load(
+          reinterpret_cast<const L16*>(sp.base + (size_t)bj * sp.stride + (size_t)row * WQ + k % WQ));
+    }
+  };
+  auto put = [&](const L16 (&v)[NL]) {
+#pragma unroll
+    for (int i = 0; i < NL; ++i) *reinterpret_cast<L16*>(Qw + (i * RPL + lr) * LDQ + col) = v[i];
+  };
+  // the LDS tile is private to the wavefront, whose LDS instructions complete in order:
+  // these only keep the compiler from moving tile accesses across each other
+  auto tile_order = [] {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
+  // consecutive products go to different accumulators (RT x TB of them)
+  auto compute = [&](int cur, int kb) {
+#pragma unroll
+    for (int kc = 0; kc < SC / 16; ++kc) {
+      T4 qv[RT];
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        const T* p = Qw + (rt * 16 + c) * LDQ + kc * 16 + 4 * g;
+        if constexpr (sizeof(T) == 8) {
+          const L16 a = *reinterpret_cast<const L16*>(p), b = *reinterpret_cast<const L16*>(p + 2);
+          qv[rt] = T4{a[0], a[1], b[0], b[1]};
+        } else {
+          qv[rt] = *reinterpret_cast<const T4*>(p);
+        }
+      }
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const int kk = kb + kc * 16 + 4 * g + s4;
+        T gv[TB];
+#pragma unroll
+        for (int tb = 0; tb < TB; ++tb)
+          gv[tb] = (NARROW && c >= TC) ? T(0) : Gs[cur][kk * TC + (NARROW ? c : tb * 16 + c)];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+          for (int tb = 0; tb < TB; ++tb) acc[rt][tb] = Mfma<T>::run(qv[rt][s4], gv[tb], acc[rt][tb]);
+      }
+    }
+  };
+  // Every G stage takes QPS Q stages, also past the last one (their loads repeat the last
+  // stage and meet zero rows of G), so that the loop issues the same loads on every path
+  // and each stage waits only for its own: into LDS, the stage two ahead into the freed
+  // registers, then the products.
+  L16 v0[NL], v1[NL];
   fetch(0);
-  stash(0);
+  stash(0, 0);
+  loadq(v0, 0);
+  __builtin_amdgcn_sched_barrier(0);  // stage 0's loads strictly before stage 1's
+  loadq(v1, min(1, nq - 1));
   __syncthreads();
   for (int st = 0; st < nst; ++st) {
     const int cur = st & 1;
-    if (st + 1 < nst) fetch(st + 1);
-    const int jn = min(U::JS, sp.nblk - st * U::JS);
-    for (int jb = 0; jb < jn; jb += PB) {
+    fetch(min(st + 1, nst - 1));
 #pragma unroll
-      for (int kc = 0; kc < VQ / 16; ++kc) {
-        const int col = kc * 16 + 4 * g;  // column of this pass
-        const int bj = jb + col / WQ;     // stored block of the stage
-        const bool bok = bj < jn;
-        const T* __restrict__ Qj = sp.base + (size_t)(st * U::JS + (bok ? bj : jb)) * sp.stride + col % WQ;
-        T4 q[RT];
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt) {
-          const int row = rowbase + rt * 16 + c;
-          q[rt] = (row < n && bok) ? *reinterpret_cast<const T4*>(Qj + (size_t)row * WQ) : T4{0, 0, 0, 0};
-        }
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const int kk = jb * WQ + col + s;
-          T gv[TB];
-#pragma unroll
-          for (int tb = 0; tb < TB; ++tb)
-            gv[tb] = (NARROW && c >= TC) ? T(0) : Gs[cur][kk * TC + (NARROW ? c : tb * 16 + c)];
-#pragma unroll
-          for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-            for (int tb = 0; tb < TB; ++tb) acc[rt][tb] = Mfma<T>::run(q[rt][s], gv[tb], acc[rt][tb]);
-        }
-      }
+    for (int qq = 0; qq < U::QPS; qq += 2) {
+      const int q = st * U::QPS + qq;
+      put(v0);
+      tile_order();
+      loadq(v0, min(q + 2, nq - 1));
+      compute(cur, qq * SC);
+      tile_order();
+      put(v1);
+      tile_order();
+      loadq(v1, min(q + 3, nq - 1));
+      compute(cur, (qq + 1) * SC);
+      tile_order();
     }
-    if (st + 1 < nst) stash(cur ^ 1);  // that buffer was last read before the previous barrier
+    stash(cur ^ 1, st + 1);  // that buffer was last read before the previous barrier
     __syncthreads();
   }
 #pragma unroll
