@@ -303,8 +303,8 @@ ecg_status ecg_debug_spmm(const ecg_operator* A, int32_t t, const double* X, dou
  * (diagonal offsets -c, -b, -a, 0, a, b, c or -c, -a, 0, a, c with b dividing c and c
  * dividing n), 3 = 3-D grid stencil with its planes staged in LDS, 4 = the same with the
  * planes brought into LDS by direct buffer loads (3 and 4: seven diagonals, a = 1, at least
- * 4 lanes of 16 bytes per block row and nx a multiple of 16 / (bytes per value); 4 also
- * needs n t and 7 n values to fit 32-bit byte offsets), 5 = SELL-C-sigma (C = 64 rows per
+ * 4 lanes of 16 bytes per block row, nx a multiple of 16 / (bytes per value), and n t and
+ * 7 n values within 32-bit byte offsets), 5 = SELL-C-sigma (C = 64 rows per
  * slice, rows sorted by length within windows of 1024; kept for matrices without a diagonal
  * form), -1 = the one the solver uses.
  * precision 0: X and Y are double, 1: float.  Row-major n x t blocks, t a power of two in

@@ -388,11 +388,14 @@ k_spmm_grid(int n, int gnx, int gny, int gnz, int ga, int zseg, int nxb, int nyb
 // x and y, (RX+2) x (K+2) block rows, once per workgroup (16 bytes per lane, contiguous
 // along x), and the tile's seven coefficient rows, into LDS; a lane then takes its x and y
 // neighbours and its coefficients from LDS and its z neighbours from registers (planes
-// z-1, z, z+1 of its own rows).  The loads of plane z+1 are issued before the terms of
-// plane z that do not need them.  Each LDS slot holds X at the linear index of its tile
-// position (zero outside [0, n)), and every term has the diagonal kernel's neighbour,
-// range test and place in the ascending chain of FMAs, so the result is bitwise that of
-// k_spmm_dia and k_spmm_grid.
+// z-1, z, z+1 of its own rows).  The loads run two planes ahead: while plane z is
+// computed, plane z+1 (already loaded) waits in registers to be written to LDS and plane
+// z+2 is in flight, so a wavefront never waits for memory it asked for in the same plane.
+// Loads go through buffer descriptors: a row outside [0, n) reads as zero with no branch,
+// so every plane issues the same loads and each wait covers only the plane it needs.  Each
+// LDS slot holds X at the linear index of its tile position (zero outside [0, n)), and
+// every term has the diagonal kernel's neighbour, range test and place in the ascending
+// chain of FMAs, so the result is bitwise that of k_spmm_dia and k_spmm_grid.
 template <typename T, int TC, int K>
 struct GridLds {
   using S = SpmmShape<T, TC>;
@@ -411,13 +414,15 @@ struct GridLds {
 
 // CW: columns of the block one workgroup takes (CW < TC splits wide blocks into column
 // groups, so that a tile of 512-byte FP64 rows keeps the x extent of a 256-byte one).
+// Needs n * TC * sizeof(T) and 7 * n * sizeof(T) below 4 GiB (32-bit buffer offsets).
 template <typename T, int TC, int CW, int K>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
 k_spmm_grid_lds(int n, int gnx, int gny, int gnz, int zseg, int nxb, int nyb, int nwork,
                 const T* __restrict__ dv, const T* __restrict__ X, T* __restrict__ Y) {
   static_assert(TC % CW == 0, "column groups");
   using G = GridLds<T, CW, K>;
   using S = typename G::S;
+  static_assert(S::VL * (int)sizeof(T) == 16, "16-byte lane chunks");
   typedef T Vec __attribute__((ext_vector_type(S::VL)));
   extern __shared__ __align__(16) unsigned char lds_raw[];
   Vec* rows_lds = reinterpret_cast<Vec*>(lds_raw);                        // [2][TY][TX][CPR]
@@ -433,14 +438,20 @@ k_spmm_grid_lds(int n, int gnx, int gny, int gnz, int zseg, int nxb, int nyb, in
   const int x0 = bx * G::RX, y0 = by * K;
   const int z0 = bz * zseg, z1 = min(gnz, z0 + zseg);
   const int x = x0 + xl;
-  const T* __restrict__ Xg = X + cg * CW;
   T* __restrict__ Yg = Y + cg * CW;
-  // linear index of tile position (yi, xi) of plane zz (halo included)
-  auto lin = [&](int zz, int yi, int xi) -> long long {
-    return (long long)zz * c + (long long)(y0 + yi - 1) * b + (x0 + xi - 1);
-  };
-  auto ldx = [&](long long r, int chunk) -> Vec {
-    return (r >= 0 && r < n) ? *reinterpret_cast<const Vec*>(Xg + (size_t)r * TC + chunk * S::VL) : Vec(0);
+  const __amdgpu_buffer_rsrc_t xr =
+      __builtin_amdgcn_make_buffer_rsrc((void*)X, 0, (int)((size_t)n * TC * sizeof(T)), 0x00020000);
+  const __amdgpu_buffer_rsrc_t cr =
+      __builtin_amdgcn_make_buffer_rsrc((void*)dv, 0, (int)((size_t)7 * n * sizeof(T)), 0x00020000);
+  constexpr unsigned kOut = 0xFFFFFFF0u;  // past the end of either buffer: reads as zero
+  // linear index of tile position (yi, xi) of plane zz (halo included); 32-bit, since
+  // n * TC * sizeof(T) < 4 GiB
+  auto lin = [&](int zz, int yi, int xi) -> int { return zz * c + (y0 + yi - 1) * b + (x0 + xi - 1); };
+  auto ldx = [&](int r, int chunk) -> Vec {
+    const unsigned off = (r >= 0 && r < n) ? (unsigned)r * (unsigned)(TC * sizeof(T)) +
+                                                 (unsigned)((cg * CW + chunk * S::VL) * sizeof(T))
+                                           : kOut;
+    return __builtin_bit_cast(Vec, __builtin_amdgcn_raw_buffer_load_b128(xr, (int)off, 0, 0));
   };
   auto halo_pos = [&](int h, int& yi, int& xi) {
     if (h < G::TX) {
@@ -455,130 +466,114 @@ k_spmm_grid_lds(int n, int gnx, int gny, int gnz, int zseg, int nxb, int nyb, in
   auto slot = [&](int buf, int yi, int xi, int chunk) -> Vec& {
     return rows_lds[(((size_t)buf * G::TY + yi) * G::TX + xi) * G::CPR + chunk];
   };
-  // coefficients of plane zz: chunk q -> (d, k, x .. x + CE - 1) of dv[d][row]
-  auto ldc = [&](int zz, int q, T (&out)[G::CE]) {
+  // coefficient chunk q of plane zz -> (d, k, x .. x + CE - 1) of dv[d][row]; rows outside
+  // [0, n) read as zero, and rows past the grid in x or y are never used
+  auto ldc = [&](int zz, int q) -> Vec {
     const int per = G::RX / G::CE;
     const int xc = (q % per) * G::CE, dk = q / per, d = dk / K, k = dk % K;
-    const long long r = (long long)zz * c + (long long)(y0 + k) * b + x0 + xc;
-    const bool rowok = zz < gnz && y0 + k < gny;
-    if (rowok && x0 + xc + G::CE <= gnx) {
-      typedef T CVec __attribute__((ext_vector_type(G::CE)));
-      const CVec v = *reinterpret_cast<const CVec*>(dv + (size_t)d * n + r);
-#pragma unroll
-      for (int e = 0; e < G::CE; ++e) out[e] = v[e];
-    } else {
-#pragma unroll
-      for (int e = 0; e < G::CE; ++e) out[e] = (rowok && x0 + xc + e < gnx) ? dv[(size_t)d * n + r + e] : T(0);
-    }
+    const int r = zz * c + (y0 + k) * b + x0 + xc;
+    const unsigned off = (q < G::CCH && r >= 0 && r < n) ? ((unsigned)d * (unsigned)n + (unsigned)r) * (unsigned)sizeof(T) : kOut;
+    return __builtin_bit_cast(Vec, __builtin_amdgcn_raw_buffer_load_b128(cr, (int)off, 0, 0));
   };
-  auto stc = [&](int buf, int q, const T (&v)[G::CE]) {
+  auto stc = [&](int buf, int q, const Vec& v) {
     const int per = G::RX / G::CE;
     const int xc = (q % per) * G::CE, dk = q / per, d = dk / K, k = dk % K;
 #pragma unroll
     for (int e = 0; e < G::CE; ++e) coef_lds[(((size_t)buf * K + k) * G::RX + xc + e) * 8 + d] = v[e];
   };
-
-  Vec prev[K], cur[K], nxt[K];
-  Vec hreg[G::HCH];
-  T creg[G::CPT][G::CE];
-  // plane z0: own rows, halo and coefficients into buffer 0; plane z0 - 1 of the own rows
+  auto load_own = [&](Vec (&o)[K], int zz) {
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    prev[k] = ldx(lin(z0 - 1, k + 1, xl + 1), li);
-    cur[k] = ldx(lin(z0, k + 1, xl + 1), li);
-  }
+    for (int k = 0; k < K; ++k) o[k] = ldx(lin(zz, k + 1, xl + 1), li);
+  };
+  auto load_rest = [&](Vec (&h)[G::HCH], Vec (&cv)[G::CPT], int zz) {
 #pragma unroll
-  for (int i = 0; i < G::HCH; ++i) {
-    const int q = tid + i * kBlock;
-    if (q < G::HALO * G::CPR) {
-      int yi, xi;
+    for (int i = 0; i < G::HCH; ++i) {
+      const int q = tid + i * kBlock;
+      int yi = 0, xi = 0;
       halo_pos(q / G::CPR, yi, xi);
-      hreg[i] = ldx(lin(z0, yi, xi), q % G::CPR);
+      h[i] = ldx(q < G::HALO * G::CPR ? lin(zz, yi, xi) : -1, q % G::CPR);
     }
-  }
 #pragma unroll
-  for (int i = 0; i < G::CPT; ++i)
-    if (tid + i * kBlock < G::CCH) ldc(z0, tid + i * kBlock, creg[i]);
+    for (int i = 0; i < G::CPT; ++i) cv[i] = ldc(zz, tid + i * kBlock);
+  };
+  auto store_plane = [&](int buf, const Vec (&o)[K], const Vec (&h)[G::HCH], const Vec (&cv)[G::CPT]) {
 #pragma unroll
-  for (int k = 0; k < K; ++k) slot(0, k + 1, xl + 1, li) = cur[k];
+    for (int k = 0; k < K; ++k) slot(buf, k + 1, xl + 1, li) = o[k];
 #pragma unroll
-  for (int i = 0; i < G::HCH; ++i) {
-    const int q = tid + i * kBlock;
-    if (q < G::HALO * G::CPR) {
-      int yi, xi;
-      halo_pos(q / G::CPR, yi, xi);
-      slot(0, yi, xi, q % G::CPR) = hreg[i];
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < G::CPT; ++i)
-    if (tid + i * kBlock < G::CCH) stc(0, tid + i * kBlock, creg[i]);
-  __syncthreads();
-
-  for (int z = z0; z < z1; ++z) {
-    const int buf = (z - z0) & 1;
-    const bool more = z + 1 < z1;
-    // loads of plane z + 1 (own rows always: they are the z + 1 neighbours)
-#pragma unroll
-    for (int k = 0; k < K; ++k) nxt[k] = ldx(lin(z + 1, k + 1, xl + 1), li);
-    if (more) {
-#pragma unroll
-      for (int i = 0; i < G::HCH; ++i) {
-        const int q = tid + i * kBlock;
-        if (q < G::HALO * G::CPR) {
-          int yi, xi;
-          halo_pos(q / G::CPR, yi, xi);
-          hreg[i] = ldx(lin(z + 1, yi, xi), q % G::CPR);
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < G::CPT; ++i)
-        if (tid + i * kBlock < G::CCH) ldc(z + 1, tid + i * kBlock, creg[i]);
-    }
-    // plane z
-    if (x < gnx) {
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        if (y0 + k >= gny) break;  // the same for the whole workgroup
-        const long long r = (long long)z * c + (long long)(y0 + k) * b + x;
-        const T* cf = coef_lds + (((size_t)buf * K + k) * G::RX + xl) * 8;
-        auto term = [&](int d, long long j, const Vec& xv, Vec& acc) {
-          fma_row<T, Vec, S::VL>(acc, (j >= 0 && j < n) ? cf[d] : T(0), xv);
-        };
-        Vec acc = Vec(0);
-        term(0, r - c, prev[k], acc);
-        term(1, r - b, slot(buf, k, xl + 1, li), acc);
-        term(2, r - 1, slot(buf, k + 1, xl, li), acc);
-        term(3, r, cur[k], acc);
-        term(4, r + 1, slot(buf, k + 1, xl + 2, li), acc);
-        term(5, r + b, slot(buf, k + 2, xl + 1, li), acc);
-        term(6, r + c, nxt[k], acc);
-        __builtin_nontemporal_store(acc, reinterpret_cast<Vec*>(Yg + (size_t)r * TC + li * S::VL));
+    for (int i = 0; i < G::HCH; ++i) {
+      const int q = tid + i * kBlock;
+      if (q < G::HALO * G::CPR) {
+        int yi, xi;
+        halo_pos(q / G::CPR, yi, xi);
+        slot(buf, yi, xi, q % G::CPR) = h[i];
       }
     }
-    if (more) {
 #pragma unroll
-      for (int k = 0; k < K; ++k) slot(buf ^ 1, k + 1, xl + 1, li) = nxt[k];
-#pragma unroll
-      for (int i = 0; i < G::HCH; ++i) {
-        const int q = tid + i * kBlock;
-        if (q < G::HALO * G::CPR) {
-          int yi, xi;
-          halo_pos(q / G::CPR, yi, xi);
-          slot(buf ^ 1, yi, xi, q % G::CPR) = hreg[i];
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < G::CPT; ++i)
-        if (tid + i * kBlock < G::CCH) stc(buf ^ 1, tid + i * kBlock, creg[i]);
-    }
-    __syncthreads();
+    for (int i = 0; i < G::CPT; ++i)
+      if (tid + i * kBlock < G::CCH) stc(buf, tid + i * kBlock, cv[i]);
+  };
+  auto compute = [&](int z, int buf, const Vec (&prev)[K], const Vec (&cur)[K], const Vec (&nxt)[K]) {
+    if (x >= gnx) return;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      prev[k] = cur[k];
-      cur[k] = nxt[k];
+      if (y0 + k >= gny) break;  // the same for the whole workgroup
+      const long long r = (long long)z * c + (long long)(y0 + k) * b + x;
+      const T* cf = coef_lds + (((size_t)buf * K + k) * G::RX + xl) * 8;
+      auto term = [&](int d, long long j, const Vec& xv, Vec& acc) {
+        fma_row<T, Vec, S::VL>(acc, (j >= 0 && j < n) ? cf[d] : T(0), xv);
+      };
+      Vec acc = Vec(0);
+      term(0, r - c, prev[k], acc);
+      term(1, r - b, slot(buf, k, xl + 1, li), acc);
+      term(2, r - 1, slot(buf, k + 1, xl, li), acc);
+      term(3, r, cur[k], acc);
+      term(4, r + 1, slot(buf, k + 1, xl + 2, li), acc);
+      term(5, r + b, slot(buf, k + 2, xl + 1, li), acc);
+      term(6, r + c, nxt[k], acc);
+      __builtin_nontemporal_store(acc, reinterpret_cast<Vec*>(Yg + (size_t)r * TC + li * S::VL));
     }
+  };
+
+  // Own rows rotate through four register sets (planes z-1, z, z+1 and the one in flight)
+  // and the halo and coefficients through two, by unrolling the plane loop four times
+  // rather than by copies: a copy of registers still being loaded would wait for them.
+  Vec o0[K], o1[K], o2[K], o3[K];
+  Vec ha[G::HCH], hb[G::HCH], ca[G::CPT], cb[G::CPT];
+  // plane z0 into buffer 0; planes z0 - 1 and z0 + 1 of the own rows and the halo and
+  // coefficients of z0 + 1 into registers
+  load_own(o0, z0 - 1);
+  load_own(o1, z0);
+  load_rest(ha, ca, z0);
+  store_plane(0, o1, ha, ca);
+  load_own(o2, z0 + 1);
+  load_rest(ha, ca, z0 + 1);
+  __syncthreads();
+  // plane z: plane z + 2 is requested (own rows while z + 2 <= z1, halo and coefficients
+  // while z + 2 < z1), plane z is computed from planes z - 1, z, z + 1 of the own rows,
+  // and plane z + 1 goes to the other LDS buffer
+  auto step = [&](int z, const Vec (&pv)[K], const Vec (&cu)[K], const Vec (&n1)[K], Vec (&n2)[K],
+                  const Vec (&h1)[G::HCH], Vec (&h2)[G::HCH], const Vec (&k1)[G::CPT], Vec (&k2)[G::CPT],
+                  bool own2, bool rest2) {
+    const int buf = (z - z0) & 1;
+    if (own2) load_own(n2, z + 2);
+    if (rest2) load_rest(h2, k2, z + 2);
+    compute(z, buf, pv, cu, n1);
+    store_plane(buf ^ 1, n1, h1, k1);  // that buffer was last read before the previous barrier
+    __syncthreads();
+  };
+  int z = z0;
+  for (; z + 5 < z1; z += 4) {
+    step(z, o0, o1, o2, o3, ha, hb, ca, cb, true, true);
+    step(z + 1, o1, o2, o3, o0, hb, ha, cb, ca, true, true);
+    step(z + 2, o2, o3, o0, o1, ha, hb, ca, cb, true, true);
+    step(z + 3, o3, o0, o1, o2, hb, ha, cb, ca, true, true);
   }
+  // at most five planes are left, starting again with the first register arrangement
+  if (z < z1) step(z, o0, o1, o2, o3, ha, hb, ca, cb, z + 2 <= z1, z + 2 < z1);
+  if (z + 1 < z1) step(z + 1, o1, o2, o3, o0, hb, ha, cb, ca, z + 3 <= z1, z + 3 < z1);
+  if (z + 2 < z1) step(z + 2, o2, o3, o0, o1, ha, hb, ca, cb, z + 4 <= z1, z + 4 < z1);
+  if (z + 3 < z1) step(z + 3, o3, o0, o1, o2, hb, ha, cb, ca, z + 5 <= z1, z + 5 < z1);
+  if (z + 4 < z1) step(z + 4, o0, o1, o2, o3, ha, hb, ca, cb, z + 6 <= z1, z + 6 < z1);
 }
 
 // The same product with the plane tiles brought into LDS by direct buffer loads (no
@@ -1754,25 +1749,24 @@ constexpr int kGridDmaK = 2;   // y rows per tile of the product fed by direct l
 
 // The LDS-staged grid kernel needs a 3-D 7-point grid stencil with unit x stride, at least 4
 // lanes per block row and rows of whole 16-byte coefficient chunks.
+// Both LDS-staged kernels read X and the coefficients through 32-bit buffer offsets.
 bool spmm_grid_lds_ok(const DevCsr& A, int tc, int elt) {
   const int vl = std::min(16 / elt, tc);
-  return A.gnx > 0 && A.ndiag == 7 && A.ga == 1 && tc / vl >= 4 && A.gnx % (16 / elt) == 0;
+  return A.gnx > 0 && A.ndiag == 7 && A.ga == 1 && tc / vl >= 4 && A.gnx % (16 / elt) == 0 &&
+         (double)A.n * tc * elt <= 4294967040.0 && (double)A.n * 7 * elt <= 4294967040.0;
 }
 
-// The direct-load variant also reads X and the coefficients through 32-bit buffer offsets.
-bool spmm_grid_dma_ok(const DevCsr& A, int tc, int elt) {
-  return spmm_grid_lds_ok(A, tc, elt) && (double)A.n * tc * elt <= 4294967040.0 &&
-         (double)A.n * 7 * elt <= 4294967040.0;
-}
+bool spmm_grid_dma_ok(const DevCsr& A, int tc, int elt) { return spmm_grid_lds_ok(A, tc, elt); }
 
 // The automatic choice: the most specific form the matrix has; among the 3-D grid-stencil
 // kernels the one measured fastest at this width and precision on the 128^3 and 160^3
-// operators (register planes, LDS-staged, or LDS fed by direct loads).
+// operators: LDS-staged for FP64 t >= 16 and FP32 t >= 32, register planes otherwise (the
+// kernel fed by direct loads is slower at every width since the LDS-staged one loads two
+// planes ahead).
 inline int spmm_choice(const DevCsr& A, int tc, int elt) {
   const int lpr = tc / std::min(16 / elt, tc);
   if (A.gnx > 0 && A.ndiag == 7 && lpr >= 4) {
-    if (elt == 8 && tc >= 16 && spmm_grid_lds_ok(A, tc, elt)) return kSpmmGridLds;
-    if (elt == 4 && (tc == 32 || tc == 64) && spmm_grid_dma_ok(A, tc, elt)) return kSpmmGridDma;
+    if (tc >= (elt == 8 ? 16 : 32) && spmm_grid_lds_ok(A, tc, elt)) return kSpmmGridLds;
     return kSpmmGrid;
   }
   if (A.ndiag > 0) return kSpmmDia;
