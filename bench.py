@@ -86,7 +86,8 @@ def form_options(args, ecg, prob, form, M=None, **extra):
     common.update(extra)
     if form == "fp64":
         return dict(common, precision=ecg.FP64), 8
-    return dict(common, precision=ecg.FP32_REFINED, inner_tol=args.inner_tol, replace_every=25, max_outer=30), 4
+    itol = args.inner_tol if args.inner_tol is not None else prob.fp32_inner_tol
+    return dict(common, precision=ecg.FP32_REFINED, inner_tol=itol, replace_every=25, max_outer=30), 4
 
 
 def run_form(args, torch, ecg, prob, op, P, b, form, M=None, steps=1, warmup=0, tag="", instrument=False,
@@ -517,7 +518,8 @@ def main():
     ap.add_argument("--t", type=int, default=32)
     ap.add_argument("--forms", default="fp64,fp32")
     ap.add_argument("--kmax", type=int, default=20000)
-    ap.add_argument("--inner-tol", type=float, default=1e-4)
+    ap.add_argument("--inner-tol", type=float, default=None,
+                    help="inner tolerance of the FP32 form (default: the workload's)")
     ap.add_argument("--q-cols", type=int, default=0)
     ap.add_argument("--progress", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true")

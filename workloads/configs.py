@@ -51,6 +51,9 @@ class Problem:
     t_min: int = 1
     tol: float = 1e-8
     kmax: int = 20000
+    # relative tolerance of each inner solve of the FP32 form with FP64 refinement: how far
+    # one FP32 solve is driven before the FP64 residual is recomputed
+    fp32_inner_tol: float = 1e-4
     extra: dict = field(default_factory=dict)
 
     @property
@@ -93,7 +96,7 @@ def config(name: str, t: int | None = None, seed: int | None = None, scale: int 
         A = fv_operator(k)
         part = box_partition((m, m, m), (4, 4, 4))
         return Problem(name, A, rhs_uniform(A.n, 5), part, 64, (m, m, m), reduce=REDUCE_REPEAT,
-                       switch_tol=1e-5, t_min=8)
+                       switch_tol=1e-5, t_min=8, fp32_inner_tol=1e-5)
     if name == "learn2d256":
         s = 0 if seed is None else int(seed)
         nx = ny = 256 // scale
